@@ -1,0 +1,158 @@
+/*
+ * fde.h -- C ABI of libfde, a GPU (MI355X, gfx950) solver for the linear
+ * systems of the implicit time discretisation of the space-fractional
+ * diffusion equation
+ *     u_t = d+ D+^a u + d- D-^a u  (+ e+ D+^b u + e- D-^b u in 2D) + f,
+ * alpha, beta in (1,2), homogeneous Dirichlet data, on a rectangle
+ * (Section 1.1, eq. (1)), preconditioned by the symbol-based tau-algebra
+ * preconditioner P_F (Section 3, eqs. prop_1D and 2D_preconditioner) of
+ * Barakitis, Ekstrom and Vassalos.
+ *
+ * Conventions for every entry point
+ *   - Vector arguments are DEVICE pointers to float64 arrays owned by the
+ *     caller, of length N = n1 (1D) or N = n1*n2 (2D).  2D arrays are stored
+ *     x-fastest, i.e. row-major with shape (n2, n1), the lexicographic order
+ *     of Section 1.4.  Input and output vectors must not overlap.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default
+ *     stream.  All calls are asynchronous on `stream`, except fde_assemble
+ *     and fde_solve, which synchronise `stream` before returning.
+ *   - A plan owns its device workspace and the copies it makes of the
+ *     coefficient arrays; it is not thread-safe: use one plan per host
+ *     thread/stream.  fde_destroy frees it.
+ *   - Errors: a negative fde_status; nothing is launched when parameters are
+ *     invalid.  fde_last_error() returns a thread-local message describing the
+ *     last failure.  FDE_ENOTCONV (> 0) means the solver stopped at maxit:
+ *     x then holds the last iterate and `info` is filled.
+ *   - Transform sizes: every n_i + 1 must be a power of two with
+ *     2 <= n_i + 1 <= 4096; other sizes return FDE_EUNSUPPORTED.
+ */
+#ifndef FDE_H
+#define FDE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fde_plan_s* fde_plan;
+
+typedef enum {
+  FDE_OK = 0,
+  FDE_ENOTCONV = 1,        /* result returned, tolerance not reached within maxit */
+  FDE_EINVAL = -1,         /* invalid parameter or argument                       */
+  FDE_ENOMEM = -2,         /* device or host allocation failed                    */
+  FDE_EHIP = -3,           /* a HIP runtime call failed                           */
+  FDE_ENONFINITE = -4,     /* NaN/Inf met in the right-hand side or a residual    */
+  FDE_EUNSUPPORTED = -5    /* a size or option this build does not handle        */
+} fde_status;
+
+/* Space discretisation (Sections 1.2 and 1.3). */
+enum { FDE_W_SHIFTED = 0,   /* first-order shifted Grunwald weights g_k, matrix T (eq. grunwaldmatrix1) */
+       FDE_W_WEIGHTED = 1   /* second-order weights w_k, matrix S (eq. grunwaldmatrix2)                 */ };
+/* Time discretisation. */
+enum { FDE_T_EULER = 0,     /* implicit Euler: M = nu I + A_x + kappa A_y, nu = h_x^a/dt (Section 1.2)     */
+       FDE_T_CN = 1         /* Crank-Nicolson: M = (1/r) I + A_x + (s/r) A_y, 1/r = 2 h_x^a/dt (Section 1.4) */ };
+/* Preconditioner. */
+enum { FDE_P_NONE = 0,      /* identity                                                                      */
+       FDE_P_TAU = 1,       /* P_F = D tau(F): D (S (x) S) diag(F) (S (x) S), F(i,j) = F_a(th_i) + kappa F_b(th_j)
+                               + shift; D = (d+ + d-)/2 (1D), (d+ + d- + e+ + e-)/4 (2D)
+                               (eq. prop_1D, eq. 2D_preconditioner)                                          */
+       FDE_P_TAU_HAT = 2,   /* constant coefficients d+- = d, e+- = e: tau(nu + d F_a + kappa e F_b), no D
+                               (Section 3.1 Case I, eq. 2D_preconditioner_proof_case)                       */
+       FDE_P_TILDE = 3      /* 1D: S diag(D_j p_a(theta_j)) S (Section 4, Table 2)                          */ };
+/* Side of the diagonal factor D in P_F. */
+enum { FDE_D_LEFT = 0,      /* P = D tau, as the text writes it: P^{-1} v = tau^{-1}(D^{-1} v) */
+       FDE_D_RIGHT = 1      /* P = tau D: P^{-1} v = D^{-1} tau^{-1} v                          */ };
+/* Krylov method. */
+enum { FDE_S_GMRES = 0,     /* right-preconditioned flexible GMRES(restart), CGS2 orthogonalisation   */
+       FDE_S_PCG = 1        /* preconditioned CG; needs a symmetric M (constant d+ = d-, e+ = e-)   */ };
+/* Arithmetic. */
+enum { FDE_FP64 = 0,        /* everything in float64                                                   */
+       FDE_MIXED = 1        /* float64 outer FGMRES (Gram-Schmidt, Givens, true residual, update, outer
+                               matvec) around a float32 inner GMRES(inner_steps) with float32 matvec
+                               and float32 tau solve; inner_steps = 0 means a float32 tau solve only   */ };
+
+typedef struct {
+  int    dim;          /* 1 or 2                                                                  */
+  int    n[2];         /* interior points n1 (x), n2 (y; ignored in 1D)                           */
+  double alpha[2];     /* fractional orders alpha (x) and beta (y), each in (1, 2)                */
+  double lo[2], hi[2]; /* domain (L1, R1) x (L2, R2); h_i = (hi - lo)/(n_i + 1)                   */
+  double dt;           /* time step h_t > 0                                                        */
+  int    weights;      /* FDE_W_*                                                                  */
+  int    time;         /* FDE_T_*                                                                  */
+  int    prec;         /* FDE_P_*                                                                  */
+  int    dside;        /* FDE_D_*                                                                  */
+  double shift;        /* added to every symbol sample of FDE_P_TAU; NaN selects the rule of
+                          Section 3.1 Case I: nu/c when all coefficients equal one constant c,
+                          0 otherwise                                                             */
+  int    solver;       /* FDE_S_*                                                                  */
+  int    restart;      /* GMRES cycle length m, 1..64                                              */
+  int    maxit;        /* cap on the total number of (outer) iterations                           */
+  double tol;          /* stop when ||b - M x||_2 <= tol ||b||_2                                   */
+  int    precision;    /* FDE_FP64 | FDE_MIXED                                                     */
+  int    inner_steps;  /* FDE_MIXED: float32 inner GMRES steps per outer step, 0..32              */
+} fde_params;
+
+typedef struct {
+  int    iters;        /* outer iterations (preconditioner applications)                          */
+  int    inner_iters;  /* float32 inner iterations (FDE_MIXED)                                    */
+  int    restarts;     /* completed GMRES cycles that did not converge                            */
+  int    converged;    /* 1 when the true relative residual is <= tol                             */
+  double relres_true;  /* ||b - M x|| / ||b|| of the returned x, computed in float64             */
+  double relres_est;   /* last Givens (GMRES) or recursive (PCG) residual estimate / ||b||       */
+  double seconds;      /* wall time of the call                                                   */
+} fde_info;
+
+/* Fills `p` with: 1D, n = 1023, alpha = 1.5 on (0,2), dt = h, FDE_W_SHIFTED,
+   FDE_T_EULER, FDE_P_TAU, FDE_D_LEFT, shift = NaN, FDE_S_GMRES, restart 30,
+   maxit 10000, tol 1e-8, FDE_FP64, inner_steps 8. */
+void fde_default_params(fde_params* p);
+
+/* Builds a plan for M and P (setup row of the method: Grunwald weights
+   (eq. grunwald1), circulant eigenvalues of T (T^T), symbol samples F at
+   theta_j = j pi/(n+1) (eq. tau_preconditioner, Theorem 2), D^{-1}).
+   dplus, dminus: device arrays of length N with d+ (x_i, y_j) >= 0, d- >= 0;
+   eplus, eminus: the y-direction coefficients (2D) or NULL (1D).  The plan
+   copies them.  Returns FDE_EINVAL when a parameter is out of range, when a
+   coefficient is negative or not finite, or when D has a zero (d+ and d- share
+   a zero, Section 3.1).  Synchronises `stream`. */
+fde_status fde_assemble(const fde_params* p,
+                        const double* dplus, const double* dminus,
+                        const double* eplus, const double* eminus,
+                        void* stream, fde_plan* out);
+
+/* y = M x (eq. first_order_1d_coefficient_matrix / eq. coef:2d), computed with
+   circulant-embedded FFT Toeplitz products.  x, y: device, length N. */
+fde_status fde_matvec(fde_plan plan, const double* x, double* y, void* stream);
+
+/* z = P^{-1} v for the plan's preconditioner: two (1D) or four (2D) DST-I
+   passes around the division by the symbol samples, and the D^{-1} scaling
+   (eqs. prop_1D, 2D_preconditioner).  v, z: device, length N. */
+fde_status fde_tau_apply(fde_plan plan, const double* v, double* z, void* stream);
+
+/* Solves M x = b (eq. linsystem).  b: device, length N.  x: device, length
+   N, holds the starting vector on entry and the solution on return.  info:
+   host pointer or NULL.  Synchronises `stream`.  b = 0 returns x = 0 with 0
+   iterations.  FDE_ENONFINITE when b or a residual is not finite. */
+fde_status fde_solve(fde_plan plan, const double* b, double* x, fde_info* info, void* stream);
+
+/* Right-hand side of one time step (Section 1.2, eq. matrixform; Section 1.4
+   for Crank-Nicolson): Euler b = nu u_prev + h_x^a f, Crank-Nicolson
+   b = (nu I - A_x - kappa A_y) u_prev + 2 h_x^a f.  f may be NULL (f = 0). */
+fde_status fde_rhs(fde_plan plan, const double* u_prev, const double* f, double* b, void* stream);
+
+/* Device bytes a plan with these parameters allocates (for admission control). */
+size_t fde_plan_bytes(const fde_params* p);
+
+/* Releases the plan (synchronises the device first). NULL is ignored. */
+void fde_destroy(fde_plan plan);
+
+/* Thread-local description of the last error, "" when none. */
+const char* fde_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDE_H */

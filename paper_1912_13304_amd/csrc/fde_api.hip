@@ -1,0 +1,1011 @@
+// C ABI of libfde (include/fde.h): plan assembly, the operator and
+// preconditioner entry points and the Krylov drivers.
+//
+// Host work is limited to O(n) float64 setup (Grunwald weights, circulant
+// eigenvalues of T by a host FFT, twiddles, symbol samples) and to enqueueing
+// kernels.  The Krylov state lives on the device (fde_krylov.hpp); the host
+// reads it back once per GMRES cycle, and polls a mapped host flag written by
+// the device one step behind the launch front so that it stops enqueueing
+// after convergence without stalling the GPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fde.h"
+#include "fde_krylov.hpp"
+#include "fde_lines.hpp"
+
+using namespace fde;
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static fde_status fail(fde_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(FDE_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),      \
+                  __FILE__, __LINE__);                                                   \
+  } while (0)
+
+extern "C" const char* fde_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// Plan
+// ---------------------------------------------------------------------------
+struct Dir {
+  int n = 0, P = 0, logP = 0, nlines = 0, B = 1, logB = 0;
+  long ls = 0, es = 0;
+};
+
+template <typename T>
+struct Consts {
+  T *dp = nullptr, *dm = nullptr, *ep = nullptr, *em = nullptr;  // coefficients
+  T* dinv = nullptr;                                             // D^{-1} (null: no D factor)
+  T *fx = nullptr, *fy = nullptr, *fzero = nullptr;              // symbol samples
+  cx<T> *W2x = nullptr, *W2y = nullptr, *lamx = nullptr, *lamy = nullptr;
+};
+
+struct fde_plan_s {
+  fde_params p;
+  int dim = 1, n1 = 0, n2 = 1;
+  long N = 0;
+  double hx = 0, hy = 0, hxa = 0, nu = 0, kappa = 0, shift = 0;
+  bool has_dinv = false;
+  int dside = FDE_D_LEFT;
+  Dir rows, cols;
+  Consts<double> c64;
+  Consts<float> c32;
+  int m = 30, kin = 0;
+  double *V = nullptr, *Z = nullptr, *t1 = nullptr, *t2 = nullptr, *t3 = nullptr;
+  float *Vf = nullptr, *t1f = nullptr, *t2f = nullptr, *t3f = nullptr, *uf = nullptr, *zf = nullptr;
+  double* part = nullptr;
+  KState *ks = nullptr, *ksi = nullptr;
+  double* hstat = nullptr;      // mapped pinned host memory
+  double* hstat_dev = nullptr;  // its device address
+  KState* hks = nullptr;        // pinned host copy of the state header
+  hipEvent_t ev[4] = {};
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+};
+
+static int ilog2(long v) {
+  int l = 0;
+  while ((1L << l) < v) ++l;
+  return l;
+}
+
+static bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Lines per workgroup for a transform of size P: B*P/8 threads per workgroup,
+// at most 1024; aim for 512 threads and enough workgroups to cover the chip.
+static void choose_tile(Dir& d) {
+  int B = std::max(1, 4096 / d.P);
+  // keep at least ~256 workgroups when there are enough lines
+  while (B > 1 && (d.nlines + B - 1) / B < 256 && B * d.P / 8 > 64) B >>= 1;
+  if (B * d.P / 8 > 1024) B = std::max(1, 8192 / d.P);
+  d.B = B;
+  d.logB = ilog2(B);
+}
+
+void fde_default_params_impl(fde_params* p) {
+  std::memset(p, 0, sizeof *p);
+  p->dim = 1;
+  p->n[0] = 1023;
+  p->n[1] = 1;
+  p->alpha[0] = 1.5;
+  p->alpha[1] = 1.5;
+  p->lo[0] = p->lo[1] = 0.0;
+  p->hi[0] = p->hi[1] = 2.0;
+  p->dt = 2.0 / 1024.0;
+  p->weights = FDE_W_SHIFTED;
+  p->time = FDE_T_EULER;
+  p->prec = FDE_P_TAU;
+  p->dside = FDE_D_LEFT;
+  p->shift = NAN;
+  p->solver = FDE_S_GMRES;
+  p->restart = 30;
+  p->maxit = 10000;
+  p->tol = 1e-8;
+  p->precision = FDE_FP64;
+  p->inner_steps = 8;
+}
+
+extern "C" void fde_default_params(fde_params* p) {
+  if (p) fde_default_params_impl(p);
+}
+
+static fde_status validate(const fde_params* p) {
+  if (!p) return fail(FDE_EINVAL, "params is NULL");
+  if (p->dim != 1 && p->dim != 2) return fail(FDE_EINVAL, "dim must be 1 or 2 (got %d)", p->dim);
+  for (int i = 0; i < p->dim; ++i) {
+    if (p->n[i] < 1) return fail(FDE_EINVAL, "n[%d] must be >= 1 (got %d)", i, p->n[i]);
+    if (!(p->alpha[i] > 1.0 && p->alpha[i] < 2.0))
+      return fail(FDE_EINVAL, "alpha[%d] must lie in (1,2) (got %g)", i, p->alpha[i]);
+    if (!(p->hi[i] > p->lo[i]) || !std::isfinite(p->hi[i]) || !std::isfinite(p->lo[i]))
+      return fail(FDE_EINVAL, "domain [%g, %g] is empty", p->lo[i], p->hi[i]);
+    if (!is_pow2((long)p->n[i] + 1) || p->n[i] + 1 > 4096)
+      return fail(FDE_EUNSUPPORTED, "n[%d] + 1 = %d must be a power of two <= 4096", i, p->n[i] + 1);
+  }
+  if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(FDE_EINVAL, "dt must be > 0 (got %g)", p->dt);
+  if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return fail(FDE_EINVAL, "tol must be > 0 (got %g)", p->tol);
+  if (p->weights != FDE_W_SHIFTED && p->weights != FDE_W_WEIGHTED) return fail(FDE_EINVAL, "bad weights");
+  if (p->time != FDE_T_EULER && p->time != FDE_T_CN) return fail(FDE_EINVAL, "bad time scheme");
+  if (p->prec < FDE_P_NONE || p->prec > FDE_P_TILDE) return fail(FDE_EINVAL, "bad preconditioner");
+  if (p->prec == FDE_P_TILDE && p->dim != 1) return fail(FDE_EINVAL, "P_tilde is defined in 1D only");
+  if (p->dside != FDE_D_LEFT && p->dside != FDE_D_RIGHT) return fail(FDE_EINVAL, "bad dside");
+  if (p->solver != FDE_S_GMRES && p->solver != FDE_S_PCG) return fail(FDE_EINVAL, "bad solver");
+  if (p->restart < 1 || p->restart > KMAX) return fail(FDE_EINVAL, "restart must be in 1..%d", KMAX);
+  if (p->maxit < 1) return fail(FDE_EINVAL, "maxit must be >= 1");
+  if (p->precision != FDE_FP64 && p->precision != FDE_MIXED) return fail(FDE_EINVAL, "bad precision");
+  if (p->precision == FDE_MIXED && (p->inner_steps < 0 || p->inner_steps > 32))
+    return fail(FDE_EINVAL, "inner_steps must be in 0..32");
+  if (p->precision == FDE_MIXED && p->solver != FDE_S_GMRES)
+    return fail(FDE_EINVAL, "the mixed form wraps an FGMRES outer loop");
+  if (!std::isnan(p->shift) && !std::isfinite(p->shift)) return fail(FDE_EINVAL, "shift must be finite or NaN");
+  return FDE_OK;
+}
+
+// Device bytes of a plan (buffers only; the kernels need no other memory).
+static size_t plan_bytes_impl(const fde_params* p) {
+  const long n1 = p->n[0], n2 = p->dim == 2 ? p->n[1] : 1;
+  const long N = n1 * n2;
+  const long m = p->restart;
+  size_t b = 0;
+  const int ncoef = p->dim == 2 ? 4 : 2;
+  b += (size_t)N * (ncoef + 1) * (8 + 4);       // coefficients and D^{-1}, both precisions
+  b += (size_t)(n1 + n2 + 1) * (8 + 4);         // symbol samples
+  b += (size_t)4 * (2 * (n1 + 1) + 2 * (n2 + 1)) * (16 + 8);  // twiddles and eigenvalues
+  if (p->solver == FDE_S_PCG) b += (size_t)N * 8 * 6;
+  else b += (size_t)N * 8 * (2 * m + 1 + 3);
+  if (p->precision == FDE_MIXED) b += (size_t)N * 4 * (p->inner_steps + 1 + 6);
+  b += (size_t)RED_MAXG * (KMAX + 1) * 8 + 2 * sizeof(KState);
+  return b;
+}
+
+extern "C" size_t fde_plan_bytes(const fde_params* p) {
+  if (validate(p) != FDE_OK) return 0;
+  return plan_bytes_impl(p);
+}
+
+template <typename T>
+static fde_status dalloc(fde_plan pl, T** ptr, size_t count) {
+  void* q = nullptr;
+  const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess) return fail(FDE_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  pl->allocs.push_back(q);
+  pl->bytes += bytes;
+  *ptr = static_cast<T*>(q);
+  return FDE_OK;
+}
+
+#define TRY(expr)                   \
+  do {                              \
+    fde_status s_ = (expr);         \
+    if (s_ != FDE_OK) return s_;    \
+  } while (0)
+
+// In-place radix-2 FFT, exponent sign -1, float64 (host setup only).
+static void host_fft(std::vector<std::complex<double>>& a) {
+  const size_t L = a.size();
+  for (size_t i = 1, j = 0; i < L; ++i) {
+    size_t bit = L >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) std::swap(a[i], a[j]);
+  }
+  for (size_t len = 2; len <= L; len <<= 1) {
+    const size_t half = len >> 1;
+    std::vector<std::complex<double>> w(half);
+    for (size_t k = 0; k < half; ++k) {
+      const double ang = -2.0 * M_PI * (double)k / (double)len;
+      w[k] = std::complex<double>(std::cos(ang), std::sin(ang));
+    }
+    for (size_t i = 0; i < L; i += len)
+      for (size_t k = 0; k < half; ++k) {
+        const std::complex<double> u = a[i + k], v = a[i + k + half] * w[k];
+        a[i + k] = u + v;
+        a[i + k + half] = u - v;
+      }
+  }
+}
+
+// Grunwald weights g_0..g_K (eq. grunwald1) or the second-order weights w_k
+// (Section 1.3), by the ratio g_k/g_{k-1} = (k - 1 - alpha)/k.
+static std::vector<double> weights(double alpha, int K, int kind) {
+  std::vector<double> g(K + 2);
+  g[0] = 1.0;
+  for (int k = 1; k <= K + 1; ++k) g[k] = g[k - 1] * ((double)(k - 1) - alpha) / (double)k;
+  if (kind == FDE_W_SHIFTED) return g;
+  std::vector<double> w(K + 2);
+  w[0] = 0.5 * alpha * g[0];
+  for (int k = 1; k <= K + 1; ++k) w[k] = 0.5 * alpha * g[k] + 0.5 * (2.0 - alpha) * g[k - 1];
+  return w;
+}
+
+// Symbol F_a(theta) = f(theta) + f(-theta) with f = g_a (first order,
+// Section 2.1: g_a(t) = -e^{-it}(1 - e^{it})^a) or w_a (second order,
+// w_a(t) = -((2 - a(1 - e^{-it}))/2)(1 - e^{it})^a); principal branch.
+static double symbol(double a, double t, int kind) {
+  auto f = [&](double th) {
+    const std::complex<double> I(0.0, 1.0);
+    const std::complex<double> base = std::pow(1.0 - std::exp(I * th), a);
+    if (kind == FDE_W_SHIFTED) return -std::exp(-I * th) * base;
+    return -((2.0 - a * (1.0 - std::exp(-I * th))) / 2.0) * base;
+  };
+  return (f(t) + f(-t)).real();
+}
+
+template <typename T>
+static fde_status upload(fde_plan pl, T** dst, const std::vector<double>& src) {
+  TRY(dalloc(pl, dst, src.size()));
+  std::vector<T> tmp(src.begin(), src.end());
+  HIPCHK(hipMemcpy(*dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice));
+  return FDE_OK;
+}
+
+template <typename T>
+static fde_status upload_cx(fde_plan pl, cx<T>** dst, const std::vector<std::complex<double>>& src) {
+  TRY(dalloc(pl, dst, src.size()));
+  std::vector<cx<T>> tmp(src.size());
+  for (size_t i = 0; i < src.size(); ++i) {
+    tmp[i].x = (T)src[i].real();
+    tmp[i].y = (T)src[i].imag();
+  }
+  HIPCHK(hipMemcpy(*dst, tmp.data(), tmp.size() * sizeof(cx<T>), hipMemcpyHostToDevice));
+  return FDE_OK;
+}
+
+// Twiddles W2[m] = exp(-i pi m/P), m < 2P, and circulant eigenvalues of the
+// 2P x 2P circulant whose leading n x n block is T (or S): first column
+// (-g_1, ..., -g_n, 0, ..., 0, -g_0).
+static fde_status direction_tables(fde_plan pl, double alpha, int n, cx<double>** W2d, cx<float>** W2f,
+                                   cx<double>** lamd, cx<float>** lamf) {
+  const int P = n + 1;
+  std::vector<std::complex<double>> W2(2 * P), lam(2 * P, 0.0);
+  for (int m = 0; m < 2 * P; ++m) {
+    // angle pi m/P, reduced by symmetry to keep the argument small
+    const double t = (double)m / (double)P;  // exact
+    W2[m] = std::complex<double>(std::cos(M_PI * t), -std::sin(M_PI * t));
+  }
+  // exact values at multiples of pi/2
+  for (int m = 0; m < 2 * P; m += std::max(1, P / 2)) {
+    const int q = (int)((2L * m) / P) & 3;
+    if ((2L * m) % P == 0) W2[m] = q == 0 ? 1.0 : q == 1 ? std::complex<double>(0, -1) : q == 2 ? -1.0 : std::complex<double>(0, 1);
+  }
+  std::vector<double> g = weights(alpha, n, pl->p.weights);
+  for (int k = 0; k < n; ++k) lam[k] = -g[k + 1];
+  lam[2 * P - 1] = -g[0];
+  host_fft(lam);
+  lam.resize(P + 1);
+  TRY(upload_cx(pl, W2d, W2));
+  TRY(upload_cx(pl, W2f, W2));
+  TRY(upload_cx(pl, lamd, lam));
+  TRY(upload_cx(pl, lamf, lam));
+  return FDE_OK;
+}
+
+static void destroy_impl(fde_plan pl) {
+  if (!pl) return;
+  (void)hipDeviceSynchronize();
+  for (void* q : pl->allocs) (void)hipFree(q);
+  if (pl->hstat) (void)hipHostFree(pl->hstat);
+  if (pl->hks) (void)hipHostFree(pl->hks);
+  for (auto& e : pl->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete pl;
+}
+
+extern "C" void fde_destroy(fde_plan pl) { destroy_impl(pl); }
+
+static fde_status coef_stats(fde_plan pl, const double* a, double* st3, hipStream_t st) {
+  double* d = nullptr;
+  TRY(dalloc(pl, &d, 3));
+  hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(RED_THREADS), 0, st, a, pl->N, d);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(st3, d, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return FDE_OK;
+}
+
+static fde_status assemble_impl(const fde_params* p, const double* dp, const double* dm, const double* ep,
+                                const double* em, hipStream_t st, fde_plan pl) {
+  pl->p = *p;
+  pl->dim = p->dim;
+  pl->n1 = p->n[0];
+  pl->n2 = p->dim == 2 ? p->n[1] : 1;
+  pl->N = (long)pl->n1 * pl->n2;
+  pl->hx = (p->hi[0] - p->lo[0]) / (pl->n1 + 1);
+  pl->hxa = std::pow(pl->hx, p->alpha[0]);
+  pl->nu = (p->time == FDE_T_EULER ? 1.0 : 2.0) * pl->hxa / p->dt;
+  if (p->dim == 2) {
+    pl->hy = (p->hi[1] - p->lo[1]) / (pl->n2 + 1);
+    pl->kappa = pl->hxa / std::pow(pl->hy, p->alpha[1]);
+  }
+  pl->dside = p->dside;
+  pl->m = p->restart;
+  pl->kin = p->precision == FDE_MIXED ? p->inner_steps : 0;
+  const long N = pl->N;
+
+  // geometry
+  pl->rows.n = pl->n1;
+  pl->rows.P = pl->n1 + 1;
+  pl->rows.logP = ilog2(pl->rows.P);
+  pl->rows.nlines = pl->n2;
+  pl->rows.ls = pl->n1;
+  pl->rows.es = 1;
+  choose_tile(pl->rows);
+  if (p->dim == 2) {
+    pl->cols.n = pl->n2;
+    pl->cols.P = pl->n2 + 1;
+    pl->cols.logP = ilog2(pl->cols.P);
+    pl->cols.nlines = pl->n1;
+    pl->cols.ls = 1;
+    pl->cols.es = pl->n1;
+    choose_tile(pl->cols);
+  }
+
+  // coefficients: validate and copy
+  const double* src[4] = {dp, dm, ep, em};
+  const int ncoef = p->dim == 2 ? 4 : 2;
+  double stats[4][3];
+  for (int i = 0; i < ncoef; ++i) {
+    if (!src[i]) return fail(FDE_EINVAL, "coefficient array %d is NULL", i);
+    TRY(coef_stats(pl, src[i], stats[i], st));
+    if (stats[i][2] != 0.0) return fail(FDE_EINVAL, "coefficient array %d has a non-finite value", i);
+    if (stats[i][0] < 0.0) return fail(FDE_EINVAL, "coefficient array %d has a negative value", i);
+  }
+  double* d64[4] = {nullptr, nullptr, nullptr, nullptr};
+  float* d32[4] = {nullptr, nullptr, nullptr, nullptr};
+  for (int i = 0; i < ncoef; ++i) {
+    TRY(dalloc(pl, &d64[i], N));
+    TRY(dalloc(pl, &d32[i], N));
+    HIPCHK(hipMemcpyAsync(d64[i], src[i], N * sizeof(double), hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL((cast_kernel<double, float>), dim3(256), dim3(256), 0, st, src[i], d32[i], N);
+    HIPCHK(hipGetLastError());
+  }
+  pl->c64.dp = d64[0];
+  pl->c64.dm = d64[1];
+  pl->c64.ep = d64[2];
+  pl->c64.em = d64[3];
+  pl->c32.dp = d32[0];
+  pl->c32.dm = d32[1];
+  pl->c32.ep = d32[2];
+  pl->c32.em = d32[3];
+
+  // constancy (Section 3.1, Case I): all coefficients one constant c
+  bool constant = true;
+  double cval = stats[0][0];
+  for (int i = 0; i < ncoef; ++i)
+    if (stats[i][0] != cval || stats[i][1] != cval) constant = false;
+
+  // D^{-1}
+  pl->has_dinv = (p->prec == FDE_P_TAU);
+  if (pl->has_dinv) {
+    TRY(dalloc(pl, &pl->c64.dinv, N));
+    TRY(dalloc(pl, &pl->c32.dinv, N));
+    if (p->dim == 2)
+      hipLaunchKernelGGL((dinv_kernel<true>), dim3(256), dim3(256), 0, st, d64[0], d64[1], d64[2], d64[3],
+                         pl->c64.dinv, pl->c32.dinv, N);
+    else
+      hipLaunchKernelGGL((dinv_kernel<false>), dim3(256), dim3(256), 0, st, d64[0], d64[1], d64[2], d64[3],
+                         pl->c64.dinv, pl->c32.dinv, N);
+    HIPCHK(hipGetLastError());
+    double ds[3];
+    TRY(coef_stats(pl, pl->c64.dinv, ds, st));
+    if (ds[2] != 0.0 || !(ds[0] > 0.0))
+      return fail(FDE_EINVAL, "D = mean of the coefficients has a zero (d+ and d- share a zero)");
+  }
+
+  // symbol samples at theta_j = j pi/(n+1)
+  const int n1 = pl->n1, n2 = pl->n2;
+  std::vector<double> Fa(n1), Fb(p->dim == 2 ? n2 : 1, 0.0);
+  for (int i = 0; i < n1; ++i) Fa[i] = symbol(p->alpha[0], M_PI * (i + 1) / (double)(n1 + 1), p->weights);
+  if (p->dim == 2)
+    for (int j = 0; j < n2; ++j) Fb[j] = symbol(p->alpha[1], M_PI * (j + 1) / (double)(n2 + 1), p->weights);
+  std::vector<double> fx(n1), fy(p->dim == 2 ? n2 : 1, 0.0), fz(1, 0.0);
+  double shift = 0.0;
+  if (p->prec == FDE_P_TAU) {
+    shift = std::isnan(p->shift) ? (constant ? pl->nu / cval : 0.0) : p->shift;
+    for (int i = 0; i < n1; ++i) fx[i] = Fa[i];
+    if (p->dim == 2)
+      for (int j = 0; j < n2; ++j) fy[j] = pl->kappa * Fb[j] + shift;
+    else
+      for (int i = 0; i < n1; ++i) fx[i] += shift;
+  } else if (p->prec == FDE_P_TAU_HAT) {
+    // constant d+- = d, e+- = e required
+    const double d = stats[0][0];
+    if (!(stats[0][0] == stats[0][1] && stats[1][0] == d && stats[1][1] == d))
+      return fail(FDE_EINVAL, "P_hat needs constant, equal d+ and d-");
+    double e = 0.0;
+    if (p->dim == 2) {
+      e = stats[2][0];
+      if (!(stats[2][0] == stats[2][1] && stats[3][0] == e && stats[3][1] == e))
+        return fail(FDE_EINVAL, "P_hat needs constant, equal e+ and e-");
+    }
+    for (int i = 0; i < n1; ++i) fx[i] = d * Fa[i];
+    if (p->dim == 2)
+      for (int j = 0; j < n2; ++j) fy[j] = pl->kappa * e * Fb[j] + pl->nu;
+    else
+      for (int i = 0; i < n1; ++i) fx[i] += pl->nu;
+    if (!(d > 0.0) || (p->dim == 2 && !(e > 0.0))) return fail(FDE_EINVAL, "P_hat needs positive coefficients");
+  } else if (p->prec == FDE_P_TILDE) {
+    std::vector<double> hp(N), hm(N);
+    HIPCHK(hipMemcpy(hp.data(), dp, N * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(hm.data(), dm, N * sizeof(double), hipMemcpyDeviceToHost));
+    for (int i = 0; i < n1; ++i) {
+      fx[i] = 0.5 * (hp[i] + hm[i]) * Fa[i];
+      if (!(fx[i] > 0.0)) return fail(FDE_EINVAL, "P_tilde: D_j p(theta_j) must be positive");
+    }
+  }
+  pl->shift = shift;
+  TRY(upload(pl, &pl->c64.fx, fx));
+  TRY(upload(pl, &pl->c32.fx, fx));
+  TRY(upload(pl, &pl->c64.fy, fy));
+  TRY(upload(pl, &pl->c32.fy, fy));
+  TRY(upload(pl, &pl->c64.fzero, fz));
+  TRY(upload(pl, &pl->c32.fzero, fz));
+  TRY(direction_tables(pl, p->alpha[0], n1, &pl->c64.W2x, &pl->c32.W2x, &pl->c64.lamx, &pl->c32.lamx));
+  if (p->dim == 2)
+    TRY(direction_tables(pl, p->alpha[1], n2, &pl->c64.W2y, &pl->c32.W2y, &pl->c64.lamy, &pl->c32.lamy));
+
+  // workspace
+  const int m = pl->m;
+  const long nvec = p->solver == FDE_S_PCG ? 3 : (m + 1);
+  TRY(dalloc(pl, &pl->V, (size_t)nvec * N));
+  TRY(dalloc(pl, &pl->Z, (size_t)(p->solver == FDE_S_PCG ? 2 : m) * N));
+  TRY(dalloc(pl, &pl->t1, N));
+  TRY(dalloc(pl, &pl->t2, N));
+  TRY(dalloc(pl, &pl->t3, N));
+  if (p->precision == FDE_MIXED) {
+    TRY(dalloc(pl, &pl->Vf, (size_t)(pl->kin + 1) * N));
+    TRY(dalloc(pl, &pl->t1f, N));
+    TRY(dalloc(pl, &pl->t2f, N));
+    TRY(dalloc(pl, &pl->t3f, N));
+    TRY(dalloc(pl, &pl->uf, N));
+    TRY(dalloc(pl, &pl->zf, N));
+  }
+  TRY(dalloc(pl, &pl->part, (size_t)RED_MAXG * (KMAX + 1)));
+  TRY(dalloc(pl, &pl->ks, 1));
+  TRY(dalloc(pl, &pl->ksi, 1));
+  HIPCHK(hipMemsetAsync(pl->ks, 0, sizeof(KState), st));
+  HIPCHK(hipMemsetAsync(pl->ksi, 0, sizeof(KState), st));
+  void* hs = nullptr;
+  HIPCHK(hipHostMalloc(&hs, 4 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
+  pl->hstat = static_cast<double*>(hs);
+  std::memset(pl->hstat, 0, 4 * sizeof(double));
+  void* hd = nullptr;
+  HIPCHK(hipHostGetDevicePointer(&hd, hs, 0));
+  pl->hstat_dev = static_cast<double*>(hd);
+  void* hk = nullptr;
+  HIPCHK(hipHostMalloc(&hk, sizeof(KState), hipHostMallocDefault));
+  pl->hks = static_cast<KState*>(hk);
+  for (auto& e : pl->ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  HIPCHK(hipStreamSynchronize(st));
+  return FDE_OK;
+}
+
+extern "C" fde_status fde_assemble(const fde_params* p, const double* dplus, const double* dminus,
+                                   const double* eplus, const double* eminus, void* stream, fde_plan* out) {
+  if (!out) return fail(FDE_EINVAL, "out is NULL");
+  *out = nullptr;
+  TRY(validate(p));
+  fde_plan pl = new (std::nothrow) fde_plan_s();
+  if (!pl) return fail(FDE_ENOMEM, "host allocation failed");
+  fde_status s = assemble_impl(p, dplus, dminus, eplus, eminus, (hipStream_t)stream, pl);
+  if (s != FDE_OK) {
+    std::string keep = g_err;
+    destroy_impl(pl);
+    g_err = keep;
+    return s;
+  }
+  *out = pl;
+  return FDE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers
+// ---------------------------------------------------------------------------
+template <typename T, bool COLS, int FL>
+static void launch_line(const Dir& d, LineArgs<T> a, hipStream_t st) {
+  a.n = d.n;
+  a.P = d.P;
+  a.logP = d.logP;
+  a.nlines = d.nlines;
+  a.B = d.B;
+  a.logB = d.logB;
+  a.LS = d.P;
+  a.ls = d.ls;
+  a.es = d.es;
+  a.ntiles = (d.nlines + d.B - 1) / d.B;
+  const int nth = d.B * d.P / 8;
+  const size_t lds = ((size_t)d.B * a.LS + 2 * d.B) * sizeof(cx<T>);
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&line_kernel<T, COLS, FL>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_set = true;
+  }
+  const int grid = 8 * ((a.ntiles + 7) / 8);
+  hipLaunchKernelGGL((line_kernel<T, COLS, FL>), dim3(grid), dim3(std::max(nth, 1)), lds, st, a);
+}
+
+static int red_grid(long N) {
+  long g = (N + (long)RED_THREADS * RED_EPT - 1) / ((long)RED_THREADS * RED_EPT);
+  return (int)std::max(1L, std::min<long>(RED_MAXG, g));
+}
+static int ew_grid(long N) { return (int)std::max(1L, std::min<long>(2048, (N + 255) / 256)); }
+
+template <typename T>
+static const Consts<T>& consts(fde_plan pl);
+template <>
+const Consts<double>& consts<double>(fde_plan pl) { return pl->c64; }
+template <>
+const Consts<float>& consts<float>(fde_plan pl) { return pl->c32; }
+
+// Toeplitz-type LineArgs for one direction.
+template <typename T>
+static LineArgs<T> toep_args(fde_plan pl, bool ydir, const int* skip) {
+  const Consts<T>& c = consts<T>(pl);
+  LineArgs<T> a{};
+  a.W2 = ydir ? c.W2y : c.W2x;
+  a.lam = ydir ? c.lamy : c.lamx;
+  a.cplus = ydir ? c.ep : c.dp;
+  a.cminus = ydir ? c.em : c.dm;
+  a.skip = skip;
+  return a;
+}
+
+// w = M v with v's DST-side factors: the general fused step used by the
+// solvers.  Computes z = P^{-1}(sc * v) (stored in z when z != null) and
+// w = M z.  With prec NONE, z = sc * v.
+template <typename T>
+static void tau_matvec(fde_plan pl, const T* v, const double* sc, T* z, T* w, T* t1, T* t2, T* t3,
+                       hipStream_t st, const int* skip) {
+  const Consts<T>& c = consts<T>(pl);
+  const bool tau = pl->p.prec != FDE_P_NONE;
+  const T* pre = (pl->has_dinv && pl->dside == FDE_D_LEFT) ? c.dinv : nullptr;
+  const T* post = (pl->has_dinv && pl->dside == FDE_D_RIGHT) ? c.dinv : nullptr;
+  if (pl->dim == 1) {
+    LineArgs<T> a = toep_args<T>(pl, false, skip);
+    a.in = v;
+    a.sc = sc;
+    a.pre = pre;
+    a.post = post;
+    a.fline = c.fzero;
+    a.felem = c.fx;
+    a.zout = z;
+    a.bscale = (T)pl->nu;
+    a.tscale = T(1);
+    a.out = w;
+    if (tau) {
+      if (z) launch_line<T, false, LF_DST1 | LF_FDST2 | LF_STOREZ | LF_TOEP>(pl->rows, a, st);
+      else launch_line<T, false, LF_DST1 | LF_FDST2 | LF_TOEP>(pl->rows, a, st);
+    } else {
+      if (z) launch_line<T, false, LF_STOREZ | LF_TOEP>(pl->rows, a, st);
+      else launch_line<T, false, LF_TOEP>(pl->rows, a, st);
+    }
+    return;
+  }
+  T* zz = z ? z : t1;   // the column pass needs z in memory
+  if (tau) {
+    // rows: DST (with D^{-1} in front for the D tau order)
+    LineArgs<T> a{};
+    a.in = v;
+    a.sc = sc;
+    a.pre = pre;
+    a.W2 = c.W2x;
+    a.out = t1;
+    a.skip = skip;
+    launch_line<T, false, LF_DST1>(pl->rows, a, st);
+    // columns: DST, divide by F, DST
+    LineArgs<T> b{};
+    b.in = t1;
+    b.fline = c.fx;
+    b.felem = c.fy;
+    b.W2 = c.W2y;
+    b.out = t2;
+    b.skip = skip;
+    launch_line<T, true, LF_DST1 | LF_FDST2>(pl->cols, b, st);
+    // rows: DST (D^{-1} after for tau D), store z, x-direction Toeplitz
+    LineArgs<T> r = toep_args<T>(pl, false, skip);
+    r.in = t2;
+    r.post = post;
+    r.zout = zz;
+    r.W2 = c.W2x;
+    r.bscale = (T)pl->nu;
+    r.tscale = T(1);
+    r.out = t3;
+    launch_line<T, false, LF_DST1 | LF_STOREZ | LF_TOEP>(pl->rows, r, st);
+  } else {
+    LineArgs<T> r = toep_args<T>(pl, false, skip);
+    r.in = v;
+    r.sc = sc;
+    r.zout = zz;
+    r.bscale = (T)pl->nu;
+    r.tscale = T(1);
+    r.out = t3;
+    launch_line<T, false, LF_STOREZ | LF_TOEP>(pl->rows, r, st);
+  }
+  // columns: y-direction Toeplitz added to the x part
+  LineArgs<T> q = toep_args<T>(pl, true, skip);
+  q.in = zz;
+  q.base = t3;
+  q.bscale = T(1);
+  q.tscale = (T)pl->kappa;
+  q.out = w;
+  launch_line<T, true, LF_TOEP | LF_EXTBASE>(pl->cols, q, st);
+}
+
+// z = P^{-1}(sc * v)
+template <typename T>
+static void tau_only(fde_plan pl, const T* v, const double* sc, T* z, T* t1, T* t2, hipStream_t st,
+                     const int* skip, const int* skip2 = nullptr) {
+  const Consts<T>& c = consts<T>(pl);
+  const T* pre = (pl->has_dinv && pl->dside == FDE_D_LEFT) ? c.dinv : nullptr;
+  const T* post = (pl->has_dinv && pl->dside == FDE_D_RIGHT) ? c.dinv : nullptr;
+  if (pl->p.prec == FDE_P_NONE) {
+    hipLaunchKernelGGL((scale_cast_kernel<T, T>), dim3(ew_grid(pl->N)), dim3(256), 0, st, v, z, pl->N, sc,
+                       skip, skip2);
+    return;
+  }
+  if (pl->dim == 1) {
+    LineArgs<T> a{};
+    a.in = v;
+    a.sc = sc;
+    a.pre = pre;
+    a.post = post;
+    a.fline = c.fzero;
+    a.felem = c.fx;
+    a.W2 = c.W2x;
+    a.out = z;
+    a.skip = skip;
+    launch_line<T, false, LF_DST1 | LF_FDST2>(pl->rows, a, st);
+    return;
+  }
+  LineArgs<T> a{};
+  a.in = v;
+  a.sc = sc;
+  a.pre = pre;
+  a.W2 = c.W2x;
+  a.out = t1;
+  a.skip = skip;
+  launch_line<T, false, LF_DST1>(pl->rows, a, st);
+  LineArgs<T> b{};
+  b.in = t1;
+  b.fline = c.fx;
+  b.felem = c.fy;
+  b.W2 = c.W2y;
+  b.out = t2;
+  b.skip = skip;
+  launch_line<T, true, LF_DST1 | LF_FDST2>(pl->cols, b, st);
+  LineArgs<T> r{};
+  r.in = t2;
+  r.post = post;
+  r.W2 = c.W2x;
+  r.out = z;
+  r.skip = skip;
+  launch_line<T, false, LF_DST1>(pl->rows, r, st);
+}
+
+// y = bscale*x + tscale*(A_x x) + tscale*kappa*(A_y x)   (bscale = nu, tscale = 1: y = M x)
+template <typename T>
+static void matvec_only(fde_plan pl, const T* x, T* y, T* t3, T bscale, T tscale, hipStream_t st,
+                        const int* skip) {
+  if (pl->dim == 1) {
+    LineArgs<T> a = toep_args<T>(pl, false, skip);
+    a.in = x;
+    a.bscale = bscale;
+    a.tscale = tscale;
+    a.out = y;
+    launch_line<T, false, LF_TOEP>(pl->rows, a, st);
+    return;
+  }
+  LineArgs<T> a = toep_args<T>(pl, false, skip);
+  a.in = x;
+  a.bscale = bscale;
+  a.tscale = tscale;
+  a.out = t3;
+  launch_line<T, false, LF_TOEP>(pl->rows, a, st);
+  LineArgs<T> q = toep_args<T>(pl, true, skip);
+  q.in = x;
+  q.base = t3;
+  q.bscale = T(1);
+  q.tscale = tscale * (T)pl->kappa;
+  q.out = y;
+  launch_line<T, true, LF_TOEP | LF_EXTBASE>(pl->cols, q, st);
+}
+
+extern "C" fde_status fde_matvec(fde_plan pl, const double* x, double* y, void* stream) {
+  if (!pl || !x || !y) return fail(FDE_EINVAL, "NULL argument");
+  matvec_only<double>(pl, x, y, pl->t3, pl->nu, 1.0, (hipStream_t)stream, nullptr);
+  HIPCHK(hipGetLastError());
+  return FDE_OK;
+}
+
+extern "C" fde_status fde_tau_apply(fde_plan pl, const double* v, double* z, void* stream) {
+  if (!pl || !v || !z) return fail(FDE_EINVAL, "NULL argument");
+  tau_only<double>(pl, v, nullptr, z, pl->t1, pl->t2, (hipStream_t)stream, nullptr);
+  HIPCHK(hipGetLastError());
+  return FDE_OK;
+}
+
+extern "C" fde_status fde_rhs(fde_plan pl, const double* u, const double* f, double* b, void* stream) {
+  if (!pl || !u || !b) return fail(FDE_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  const long N = pl->N;
+  if (pl->p.time == FDE_T_EULER) {
+    hipLaunchKernelGGL(axpby_kernel, dim3(ew_grid(N)), dim3(256), 0, st, pl->nu, u, pl->hxa, f, b, N);
+  } else {
+    matvec_only<double>(pl, u, b, pl->t3, pl->nu, -1.0, st, nullptr);
+    if (f) hipLaunchKernelGGL(axpby_kernel, dim3(ew_grid(N)), dim3(256), 0, st, 1.0, b, 2.0 * pl->hxa, f, b, N);
+  }
+  HIPCHK(hipGetLastError());
+  return FDE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Solvers
+// ---------------------------------------------------------------------------
+__global__ void ks_init_kernel(KState* ks, int maxit, int m, double tol) {
+  if (threadIdx.x != 0) return;
+  ks->kdone = 0;
+  ks->done = 0;
+  ks->conv = 0;
+  ks->iters = 0;
+  ks->maxit = maxit;
+  ks->m = m;
+  ks->nonfinite = 0;
+  ks->breakdown = 0;
+  ks->bnorm = 0;
+  ks->tolabs = tol;   // multiplied by ||b|| once it is known
+  ks->beta = ks->est = ks->hn = 0;
+  ks->rz = ks->pq = ks->alpha = ks->betacg = 0;
+  ks->counter = 0;
+  for (int i = 0; i <= KMAX; ++i) ks->scale[i] = 0.0;
+}
+
+__global__ void ks_settol_kernel(KState* ks) {
+  if (threadIdx.x == 0) ks->tolabs = ks->tolabs * ks->bnorm;
+}
+
+template <typename T>
+static void mdot(fde_plan pl, const T* V, long ldv, int k, const T* w, KState* ks, int mode, hipStream_t st,
+                 const int* skip, const int* skip2) {
+  hipLaunchKernelGGL((mdot_kernel<T>), dim3(red_grid(pl->N)), dim3(RED_THREADS), 0, st, V, ldv, k, w, pl->N,
+                     pl->part, ks, mode, skip, skip2);
+}
+
+template <typename T>
+static void maxpy(fde_plan pl, const T* V, long ldv, int k, T* w, int cmode, KState* ks, int emode, int col,
+                  double* hstat, hipStream_t st, const int* skip, const int* skip2) {
+  hipLaunchKernelGGL((maxpy_kernel<T>), dim3(red_grid(pl->N)), dim3(RED_THREADS), 0, st, V, ldv, k, w, w, pl->N,
+                     cmode, pl->part, ks, emode, col, hstat, skip, skip2);
+}
+
+// CGS2 of w (= basis slot j+1) against basis vectors 0..j, then the Givens
+// column j.
+template <typename T>
+static void cgs2_givens(fde_plan pl, const T* V, T* w, int j, KState* ks, double* hstat, hipStream_t st,
+                        const int* skip, const int* skip2) {
+  const long N = pl->N;
+  mdot<T>(pl, V, N, j + 1, w, ks, EP_H1, st, skip, skip2);
+  maxpy<T>(pl, V, N, j + 1, w, EP_H1, ks, EP_NONE, j, nullptr, st, skip, skip2);
+  mdot<T>(pl, V, N, j + 1, w, ks, EP_H2, st, skip, skip2);
+  maxpy<T>(pl, V, N, j + 1, w, EP_H2, ks, EP_GIVENS, j, hstat, st, skip, skip2);
+}
+
+static fde_status read_header(fde_plan pl, KState* ks, hipStream_t st) {
+  HIPCHK(hipMemcpyAsync(pl->hks, ks, KSTATE_HEADER, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return FDE_OK;
+}
+
+// One outer Arnoldi step j: z_j = P^{-1} v_j (FP64, or the float32 inner
+// solve), w = M z_j into basis slot j+1, CGS2, Givens.
+static void outer_step(fde_plan pl, int j, hipStream_t st) {
+  const long N = pl->N;
+  KState* ks = pl->ks;
+  const int* skip = &ks->done;
+  double* vj = pl->V + (long)j * N;
+  double* w = pl->V + (long)(j + 1) * N;
+  double* zj = pl->Z + (long)j * N;
+  if (pl->p.precision == FDE_FP64) {
+    tau_matvec<double>(pl, vj, &ks->scale[j], zj, w, pl->t1, pl->t2, pl->t3, st, skip);
+  } else {
+    KState* ki = pl->ksi;
+    const int* s2 = &ki->done;
+    if (pl->kin == 0) {
+      hipLaunchKernelGGL((scale_cast_kernel<double, float>), dim3(ew_grid(N)), dim3(256), 0, st, vj, pl->uf, N,
+                         &ks->scale[j], skip, nullptr);
+    } else {
+      float* Vf = pl->Vf;
+      hipLaunchKernelGGL((scale_cast_kernel<double, float>), dim3(ew_grid(N)), dim3(256), 0, st, vj, Vf, N,
+                         &ks->scale[j], skip, nullptr);
+      hipLaunchKernelGGL((norm_kernel<float>), dim3(red_grid(N)), dim3(RED_THREADS), 0, st, Vf, nullptr, nullptr, N,
+                         pl->part, ki, EP_INNER0, skip, nullptr);
+      for (int i = 0; i < pl->kin; ++i) {
+        float* vi = Vf + (long)i * N;
+        float* wi = Vf + (long)(i + 1) * N;
+        // inner kernels skip when the outer cycle is over or the inner one broke down
+        tau_matvec<float>(pl, vi, &ki->scale[i], nullptr, wi, pl->t1f, pl->t2f, pl->t3f, st, s2);
+        cgs2_givens<float>(pl, Vf, wi, i, ki, nullptr, st, s2, skip);
+      }
+      hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(64), 0, st, ki, skip);
+      hipLaunchKernelGGL((update_kernel<float, float>), dim3(ew_grid(N)), dim3(RED_THREADS), 0, st, Vf, N,
+                         (const float*)nullptr, pl->uf, N, ki, ki->scale, skip);
+    }
+    tau_only<float>(pl, pl->uf, nullptr, pl->zf, pl->t1f, pl->t2f, st, skip);
+    hipLaunchKernelGGL((scale_cast_kernel<float, double>), dim3(ew_grid(N)), dim3(256), 0, st, pl->zf, zj, N,
+                       nullptr, skip, nullptr);
+    matvec_only<double>(pl, zj, w, pl->t3, pl->nu, 1.0, st, skip);
+  }
+  cgs2_givens<double>(pl, pl->V, w, j, ks, pl->hstat_dev, st, skip, nullptr);
+}
+
+// r = b - M x into basis slot 0 and its norm (cycle start / true residual).
+static void residual(fde_plan pl, const double* b, const double* x, hipStream_t st) {
+  double* tmp = pl->V + pl->N;   // slot 1 is free between cycles
+  matvec_only<double>(pl, x, tmp, pl->t3, pl->nu, 1.0, st, nullptr);
+  hipLaunchKernelGGL((norm_kernel<double>), dim3(red_grid(pl->N)), dim3(RED_THREADS), 0, st, b, tmp, pl->V, pl->N,
+                     pl->part, pl->ks, EP_RESID, nullptr, nullptr);
+}
+
+static fde_status solve_gmres(fde_plan pl, const double* b, double* x, fde_info* info, hipStream_t st) {
+  const long N = pl->N;
+  KState* ks = pl->ks;
+  hipLaunchKernelGGL(ks_init_kernel, dim3(1), dim3(1), 0, st, ks, pl->p.maxit, pl->m, pl->p.tol);
+  hipLaunchKernelGGL(ks_init_kernel, dim3(1), dim3(1), 0, st, pl->ksi, 1 << 30, std::max(1, pl->kin), 0.0);
+  hipLaunchKernelGGL((norm_kernel<double>), dim3(red_grid(N)), dim3(RED_THREADS), 0, st, b, (const double*)nullptr,
+                     (double*)nullptr, N, pl->part, ks, EP_BNORM, nullptr, nullptr);
+  hipLaunchKernelGGL(ks_settol_kernel, dim3(1), dim3(1), 0, st, ks);
+  residual(pl, b, x, st);
+  HIPCHK(hipGetLastError());
+  TRY(read_header(pl, ks, st));
+  if (pl->hks->nonfinite && !std::isfinite(pl->hks->bnorm))
+    return fail(FDE_ENONFINITE, "the right-hand side has a non-finite value");
+  if (pl->hks->bnorm == 0.0) {
+    hipLaunchKernelGGL(axpby_kernel, dim3(ew_grid(N)), dim3(256), 0, st, 0.0, b, 0.0, (const double*)nullptr, x, N);
+    HIPCHK(hipStreamSynchronize(st));
+    if (info) *info = fde_info{0, 0, 0, 1, 0.0, 0.0, 0.0};
+    return FDE_OK;
+  }
+  int restarts = 0;
+  while (!pl->hks->conv && !pl->hks->nonfinite && pl->hks->iters < pl->p.maxit) {
+    pl->hstat[0] = 0.0;
+    for (int j = 0; j < pl->m; ++j) {
+      if (j >= 2) {
+        HIPCHK(hipEventSynchronize(pl->ev[(j - 2) & 3]));
+        if (*(volatile double*)&pl->hstat[0] != 0.0) break;
+      }
+      outer_step(pl, j, st);
+      HIPCHK(hipEventRecord(pl->ev[j & 3], st));
+    }
+    hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(64), 0, st, ks, (const int*)nullptr);
+    hipLaunchKernelGGL((update_kernel<double, double>), dim3(ew_grid(N)), dim3(RED_THREADS), 0, st, pl->Z, N, x, x,
+                       N, ks, (const double*)nullptr, (const int*)nullptr);
+    residual(pl, b, x, st);
+    HIPCHK(hipGetLastError());
+    TRY(read_header(pl, ks, st));
+    if (!pl->hks->conv) ++restarts;
+  }
+  const KState& h = *pl->hks;
+  if (info) {
+    info->iters = h.iters;
+    info->restarts = restarts;
+    info->converged = h.conv;
+    info->relres_true = h.beta / h.bnorm;
+    info->relres_est = h.est / h.bnorm;
+    info->inner_iters = 0;
+    if (pl->p.precision == FDE_MIXED) {
+      TRY(read_header(pl, pl->ksi, st));
+      info->inner_iters = pl->hks->iters;
+      TRY(read_header(pl, ks, st));
+    }
+  }
+  if (h.nonfinite) return fail(FDE_ENONFINITE, "a residual became non-finite");
+  if (!h.conv) return fail(FDE_ENOTCONV, "tolerance not reached in %d iterations", h.iters);
+  return FDE_OK;
+}
+
+static fde_status solve_pcg(fde_plan pl, const double* b, double* x, fde_info* info, hipStream_t st) {
+  const long N = pl->N;
+  KState* ks = pl->ks;
+  const int* skip = &ks->done;
+  double* r = pl->V;
+  double* p = pl->V + N;
+  double* q = pl->V + 2 * N;
+  double* z = pl->Z;
+  hipLaunchKernelGGL(ks_init_kernel, dim3(1), dim3(1), 0, st, ks, pl->p.maxit, 1, pl->p.tol);
+  hipLaunchKernelGGL((norm_kernel<double>), dim3(red_grid(N)), dim3(RED_THREADS), 0, st, b, (const double*)nullptr,
+                     (double*)nullptr, N, pl->part, ks, EP_BNORM, nullptr, nullptr);
+  hipLaunchKernelGGL(ks_settol_kernel, dim3(1), dim3(1), 0, st, ks);
+  matvec_only<double>(pl, x, q, pl->t3, pl->nu, 1.0, st, nullptr);
+  hipLaunchKernelGGL((norm_kernel<double>), dim3(red_grid(N)), dim3(RED_THREADS), 0, st, b, q, r, N, pl->part, ks,
+                     EP_RESID, nullptr, nullptr);
+  HIPCHK(hipGetLastError());
+  TRY(read_header(pl, ks, st));
+  if (!std::isfinite(pl->hks->bnorm)) return fail(FDE_ENONFINITE, "the right-hand side has a non-finite value");
+  if (pl->hks->bnorm == 0.0) {
+    hipLaunchKernelGGL(axpby_kernel, dim3(ew_grid(N)), dim3(256), 0, st, 0.0, b, 0.0, (const double*)nullptr, x, N);
+    HIPCHK(hipStreamSynchronize(st));
+    if (info) *info = fde_info{0, 0, 0, 1, 0.0, 0.0, 0.0};
+    return FDE_OK;
+  }
+  int restarts = 0;
+  while (!pl->hks->conv && !pl->hks->nonfinite && pl->hks->iters < pl->p.maxit) {
+    // (re)start: z = P^{-1} r, rz = r.z, p = z
+    tau_only<double>(pl, r, nullptr, z, pl->t1, pl->t2, st, skip);
+    hipLaunchKernelGGL((dot_kernel<double>), dim3(red_grid(N)), dim3(RED_THREADS), 0, st, r, z, N, pl->part, ks,
+                       EP_CG_RZ, skip);
+    hipLaunchKernelGGL((scale_cast_kernel<double, double>), dim3(ew_grid(N)), dim3(256), 0, st, z, p, N,
+                       (const double*)nullptr, skip, (const int*)nullptr);
+    pl->hstat[0] = 0.0;
+    for (int it = 0; it < pl->p.maxit; ++it) {
+      if (it >= 2) {
+        HIPCHK(hipEventSynchronize(pl->ev[(it - 2) & 3]));
+        if (*(volatile double*)&pl->hstat[0] != 0.0) break;
+      }
+      matvec_only<double>(pl, p, q, pl->t3, pl->nu, 1.0, st, skip);
+      hipLaunchKernelGGL((dot_kernel<double>), dim3(red_grid(N)), dim3(RED_THREADS), 0, st, p, q, N, pl->part, ks,
+                         EP_CG_PQ, skip);
+      hipLaunchKernelGGL(cg_update_kernel, dim3(red_grid(N)), dim3(RED_THREADS), 0, st, x, r, p, q, N, pl->part,
+                         ks, pl->hstat_dev, skip);
+      tau_only<double>(pl, r, nullptr, z, pl->t1, pl->t2, st, skip);
+      hipLaunchKernelGGL((dot_kernel<double>), dim3(red_grid(N)), dim3(RED_THREADS), 0, st, r, z, N, pl->part, ks,
+                         EP_CG_RZ, skip);
+      hipLaunchKernelGGL(cg_direction_kernel, dim3(ew_grid(N)), dim3(256), 0, st, p, z, N, ks, skip);
+      HIPCHK(hipEventRecord(pl->ev[it & 3], st));
+    }
+    // true residual
+    matvec_only<double>(pl, x, q, pl->t3, pl->nu, 1.0, st, nullptr);
+    hipLaunchKernelGGL((norm_kernel<double>), dim3(red_grid(N)), dim3(RED_THREADS), 0, st, b, q, r, N, pl->part, ks,
+                       EP_RESID, nullptr, nullptr);
+    HIPCHK(hipGetLastError());
+    TRY(read_header(pl, ks, st));
+    if (!pl->hks->conv) ++restarts;
+  }
+  const KState& h = *pl->hks;
+  if (info) {
+    info->iters = h.iters;
+    info->inner_iters = 0;
+    info->restarts = restarts;
+    info->converged = h.conv;
+    info->relres_true = h.beta / h.bnorm;
+    info->relres_est = h.est / h.bnorm;
+  }
+  if (h.nonfinite) return fail(FDE_ENONFINITE, "a residual became non-finite");
+  if (!h.conv) return fail(FDE_ENOTCONV, "tolerance not reached in %d iterations", h.iters);
+  return FDE_OK;
+}
+
+extern "C" fde_status fde_solve(fde_plan pl, const double* b, double* x, fde_info* info, void* stream) {
+  if (!pl || !b || !x) return fail(FDE_EINVAL, "NULL argument");
+  auto t0 = std::chrono::steady_clock::now();
+  fde_status s = pl->p.solver == FDE_S_PCG ? solve_pcg(pl, b, x, info, (hipStream_t)stream)
+                                           : solve_gmres(pl, b, x, info, (hipStream_t)stream);
+  if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return s;
+}

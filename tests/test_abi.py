@@ -1,0 +1,78 @@
+"""The C-ABI library loads, exports every entry point declared in
+include/fde.h, and validates parameters on the host before any device work
+(these calls run without a GPU)."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "fde.h")).read()
+    return sorted(set(re.findall(r"\b(fde_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def fde():
+    from paper_1912_13304_amd import fde as m
+    if not os.path.exists(m.LIB_PATH):
+        pytest.skip("libfde.so not built")
+    m.load()
+    return m
+
+
+def test_every_declared_symbol_is_exported(fde):
+    lib = ctypes.CDLL(fde.LIB_PATH)
+    syms = header_symbols()
+    assert "fde_solve" in syms and "fde_assemble" in syms
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(fde.EXPORTED) <= set(syms)
+
+
+def test_struct_layout_matches_header(fde):
+    # field order and sizes of the ctypes mirrors follow include/fde.h
+    assert ctypes.sizeof(fde.FdeParams) == 4 + 8 + 4 + 16 * 3 + 8 + 16 + 8 + 12 + 4 + 8 + 8
+    assert ctypes.sizeof(fde.FdeInfo) == 16 + 24
+
+
+def test_defaults(fde):
+    p = fde.fde_default_params()
+    assert p.dim == 1 and p.n[0] == 1023 and p.restart == 30 and math.isnan(p.shift)
+    assert p.tol == 1e-8 and p.prec == fde.P_TAU and p.dside == fde.D_LEFT
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("dim", 3, -1), ("alpha", (1.0, 1.5), -1), ("alpha", (2.0, 1.5), -1), ("dt", 0.0, -1),
+    ("tol", -1.0, -1), ("restart", 0, -1), ("restart", 65, -1), ("maxit", 0, -1),
+    ("n", (1000, 1), -5), ("n", (0, 1), -1), ("prec", 9, -1), ("solver", 5, -1),
+])
+def test_invalid_parameters_rejected_before_device_work(fde, field, value, status):
+    p = fde.fde_default_params()
+    if isinstance(value, tuple):
+        for i, v in enumerate(value):
+            getattr(p, field)[i] = v
+    else:
+        setattr(p, field, value)
+    plan = ctypes.c_void_p()
+    st = fde.load().fde_assemble(ctypes.byref(p), None, None, None, None, None, ctypes.byref(plan))
+    assert st == status
+    assert not plan.value
+    assert fde.fde_last_error() != ""
+    assert fde.fde_plan_bytes(p) == 0
+
+
+def test_plan_bytes_grows_with_size(fde):
+    p = fde.fde_default_params()
+    a = fde.fde_plan_bytes(p)
+    p.dim = 2
+    p.n[0] = p.n[1] = 1023
+    b = fde.fde_plan_bytes(p)
+    p.precision = fde.MIXED
+    c = fde.fde_plan_bytes(p)
+    assert 0 < a < b < c
+    assert b > 62 * 1023 * 1023 * 8   # 2m+1 basis vectors of N float64

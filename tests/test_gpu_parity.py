@@ -1,0 +1,270 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.  Transforms must agree to a few ulps times log n
+(relative 1e-12); FP64 solves mirror the oracle's build-mode FGMRES / PCG to a
+relative 1e-10 with iteration counts within one."""
+import math
+
+import numpy as np
+import pytest
+
+import fde_inputs as fi
+from gpu_util import dev, host, need_gpu, relerr, torch
+from oracle import krylov, precond as pc
+from oracle.system import FDESystem
+
+pytestmark = pytest.mark.gpu
+
+SHAPES_1D = [1, 3, 7, 15, 63, 255, 1023, 4095]
+SHAPES_2D = [(7, 3), (15, 31), (63, 63), (127, 255), (255, 127)]
+
+
+def prob1d(n, alpha=1.37, weights="shifted", time="euler", seed=11):
+    p = fi.variable_1d(n=n, alpha=alpha, seed=seed, steps=1)
+    p.weights, p.time = weights, time
+    return p
+
+
+def prob2d(n1, n2, ax=1.7, ay=1.4, weights="shifted", time="euler", seed=12):
+    p = fi.variable_2d(n=n1, n2=n2, ax=ax, ay=ay, seed=seed, steps=1)
+    p.weights, p.time = weights, time
+    return p
+
+
+def rng_vec(N, seed):
+    return np.random.default_rng(seed).uniform(-1, 1, N)
+
+
+@pytest.mark.parametrize("n", SHAPES_1D)
+@pytest.mark.parametrize("weights,time", [("shifted", "euler"), ("weighted", "cn")])
+def test_matvec_1d(n, weights, time):
+    fde = need_gpu()
+    p = prob1d(n, weights=weights, time=time)
+    s = FDESystem.from_problem(p)
+    x = rng_vec(s.N, n)
+    with fde.Plan(p) as plan:
+        y = torch.empty(s.N, dtype=torch.float64, device="cuda")
+        plan.matvec(dev(x), y)
+        assert relerr(host(y), s.matvec(x)) < 1e-12
+
+
+@pytest.mark.parametrize("n1,n2", SHAPES_2D + [(1, 1), (3, 7)])
+@pytest.mark.parametrize("weights,time", [("shifted", "euler"), ("weighted", "cn")])
+def test_matvec_2d(n1, n2, weights, time):
+    fde = need_gpu()
+    p = prob2d(n1, n2, weights=weights, time=time)
+    s = FDESystem.from_problem(p)
+    x = rng_vec(s.N, n1 * 7 + n2)
+    with fde.Plan(p) as plan:
+        y = torch.empty(s.N, dtype=torch.float64, device="cuda")
+        plan.matvec(dev(x), y)
+        assert relerr(host(y), s.matvec(x)) < 1e-12
+
+
+@pytest.mark.parametrize("n", SHAPES_1D)
+@pytest.mark.parametrize("dside", ["left", "right"])
+def test_tau_1d(n, dside):
+    fde = need_gpu()
+    p = prob1d(n)
+    s = FDESystem.from_problem(p)
+    P = pc.make("tau", s, dside=dside)
+    v = rng_vec(s.N, 3 * n)
+    with fde.Plan(p, dside=fde.D_LEFT if dside == "left" else fde.D_RIGHT) as plan:
+        z = torch.empty(s.N, dtype=torch.float64, device="cuda")
+        plan.tau_apply(dev(v), z)
+        assert relerr(host(z), P(v)) < 1e-12
+
+
+@pytest.mark.parametrize("n1,n2", SHAPES_2D)
+@pytest.mark.parametrize("dside", ["left", "right"])
+def test_tau_2d(n1, n2, dside):
+    fde = need_gpu()
+    p = prob2d(n1, n2)
+    s = FDESystem.from_problem(p)
+    P = pc.make("tau", s, dside=dside)
+    v = rng_vec(s.N, 5 * n1 + n2)
+    with fde.Plan(p, dside=fde.D_LEFT if dside == "left" else fde.D_RIGHT) as plan:
+        z = torch.empty(s.N, dtype=torch.float64, device="cuda")
+        plan.tau_apply(dev(v), z)
+        assert relerr(host(z), P(v)) < 1e-12
+
+
+@pytest.mark.parametrize("kind", ["tau_hat", "tilde", "none", "tau_shift"])
+def test_tau_variants(kind):
+    fde = need_gpu()
+    if kind == "tau_hat":
+        p = fi.constant_1d(n=255)
+        pk = dict(prec=fde.P_TAU_HAT)
+    elif kind == "tilde":
+        p = prob1d(255)
+        pk = dict(prec=fde.P_TILDE)
+    elif kind == "none":
+        p = prob2d(31, 15)
+        pk = dict(prec=fde.P_NONE)
+    else:
+        p = prob2d(31, 15)
+        pk = dict(shift=0.37)
+    s = FDESystem.from_problem(p)
+    P = pc.make(kind if kind != "tau_shift" else "tau", s, shift=0.37 if kind == "tau_shift" else None) \
+        if kind not in ("tau_hat", "tilde", "none") else pc.make(kind, s)
+    v = rng_vec(s.N, 99)
+    with fde.Plan(p, **pk) as plan:
+        z = torch.empty(s.N, dtype=torch.float64, device="cuda")
+        plan.tau_apply(dev(v), z)
+        assert relerr(host(z), P(v)) < 1e-12
+
+
+def test_tau_hat_2d_constant():
+    fde = need_gpu()
+    n1, n2 = 63, 31
+    x, _ = fi.grid(n1, 0, 2)
+    y, _ = fi.grid(n2, 0, 2)
+    p = prob2d(n1, n2)
+    p.dplus = np.full((n2, n1), 1.3)
+    p.dminus = np.full((n2, n1), 1.3)
+    p.eplus = np.full((n2, n1), 0.6)
+    p.eminus = np.full((n2, n1), 0.6)
+    s = FDESystem.from_problem(p)
+    P = pc.make("tau_hat", s)
+    v = rng_vec(s.N, 5)
+    with fde.Plan(p, prec=fde.P_TAU_HAT) as plan:
+        z = torch.empty(s.N, dtype=torch.float64, device="cuda")
+        plan.tau_apply(dev(v), z)
+        assert relerr(host(z), P(v)) < 1e-12
+
+
+@pytest.mark.parametrize("time", ["euler", "cn"])
+def test_rhs(time):
+    fde = need_gpu()
+    p = prob2d(63, 31, weights="weighted" if time == "cn" else "shifted", time=time)
+    s = FDESystem.from_problem(p)
+    u = rng_vec(s.N, 1)
+    f = rng_vec(s.N, 2)
+    with fde.Plan(p) as plan:
+        b = torch.empty(s.N, dtype=torch.float64, device="cuda")
+        plan.rhs(dev(u), b, f=dev(f))
+        assert relerr(host(b), s.rhs(u, f)) < 1e-12
+        plan.rhs(dev(u), b)
+        assert relerr(host(b), s.rhs(u)) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Solves
+# ---------------------------------------------------------------------------
+def oracle_solve(p, b, x0, dside="left", restart=30, tol=1e-8, solver="gmres"):
+    s = FDESystem.from_problem(p)
+    P = pc.make("tau", s, dside=dside)
+    if solver == "pcg":
+        return krylov.pcg(s.matvec, b, P, x0=x0, tol=tol)
+    return krylov.fgmres(s.matvec, b, P, x0=x0, restart=restart, tol=tol)
+
+
+def gpu_solve(fde, p, b, x0, **kw):
+    with fde.Plan(p, **kw) as plan:
+        x = dev(x0)
+        info = plan.solve(dev(b), x)
+        return host(x), info
+
+
+@pytest.mark.parametrize("n,alpha,restart", [(7, 1.5, 30), (63, 1.2, 30), (255, 1.5, 30), (1023, 1.8, 30),
+                                              (4095, 1.3, 30), (7, 1.5, 5), (63, 1.2, 5), (255, 1.5, 5),
+                                              (1023, 1.8, 5)])
+def test_fgmres_1d(n, alpha, restart):
+    fde = need_gpu()
+    p = fi.variable_1d(n=n, alpha=alpha, seed=n)
+    s = FDESystem.from_problem(p)
+    b = s.rhs(p.u0)
+    xo, io = oracle_solve(p, b, p.u0, restart=restart)
+    xg, ig = gpu_solve(fde, p, b, p.u0, restart=restart)
+    assert ig.converged and io["converged"]
+    assert abs(ig.iters - io["iters"]) <= 1, (ig.iters, io["iters"])
+    assert relerr(xg, xo) < 1e-10
+    assert ig.relres_true <= 1e-8
+    assert relerr(s.matvec(xg), b) <= 1e-8 * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("n1,n2", [(15, 15), (63, 31), (127, 127), (255, 255)])
+@pytest.mark.parametrize("dside", ["left", "right"])
+def test_fgmres_2d(n1, n2, dside):
+    fde = need_gpu()
+    p = fi.variable_2d(n=n1, n2=n2, seed=n1 + n2)
+    s = FDESystem.from_problem(p)
+    b = s.rhs(p.u0.reshape(-1))
+    x0 = p.u0.reshape(-1)
+    xo, io = oracle_solve(p, b, x0, dside=dside)
+    xg, ig = gpu_solve(fde, p, b, x0, dside=fde.D_LEFT if dside == "left" else fde.D_RIGHT)
+    assert ig.converged and io["converged"]
+    assert abs(ig.iters - io["iters"]) <= 1, (ig.iters, io["iters"])
+    assert relerr(xg, xo) < 1e-10
+    assert relerr(s.matvec(xg), b) <= 1e-8 * (1 + 1e-6)
+
+
+def test_fgmres_many_restarts():
+    """GMRES(5) on n = 4095, alpha = 1.3 needs about a thousand iterations
+    (over 200 restarts).  Rounding differences between two FP64 orders of
+    evaluation move the stopping point by a few iterations there; the counts
+    must agree to 0.5% and both solutions must meet the tolerance."""
+    fde = need_gpu()
+    p = fi.variable_1d(n=4095, alpha=1.3, seed=4095)
+    s = FDESystem.from_problem(p)
+    b = s.rhs(p.u0)
+    xo, io = oracle_solve(p, b, p.u0, restart=5)
+    xg, ig = gpu_solve(fde, p, b, p.u0, restart=5)
+    assert ig.converged and io["converged"]
+    assert abs(ig.iters - io["iters"]) <= max(1, 0.005 * io["iters"]), (ig.iters, io["iters"])
+    assert relerr(s.matvec(xg), b) <= 1e-8 * (1 + 1e-6)
+    assert relerr(xg, xo) < 1e-6
+
+
+def test_pcg_constant_1d_full_size():
+    """1D constant coefficients, n = 1023, alpha = 1.5, dt = h, PCG with the
+    Case I shifted tau preconditioner to 1e-10."""
+    fde = need_gpu()
+    p = fi.constant_1d()
+    xo, io = oracle_solve(p, p.b, np.zeros(p.N), tol=1e-10, solver="pcg")
+    xg, ig = gpu_solve(fde, p, p.b, np.zeros(p.N))
+    assert ig.converged and io["converged"]
+    assert abs(ig.iters - io["iters"]) <= 1, (ig.iters, io["iters"])
+    assert relerr(xg, xo) < 1e-10
+
+
+def test_zero_rhs_and_nonfinite():
+    fde = need_gpu()
+    p = fi.variable_1d(n=63)
+    with fde.Plan(p) as plan:
+        x = dev(np.ones(63))
+        info = plan.solve(dev(np.zeros(63)), x)
+        assert info.iters == 0 and info.converged
+        assert np.all(host(x) == 0)
+        b = np.ones(63)
+        b[5] = np.nan
+        with pytest.raises(fde.FdeError) as e:
+            plan.solve(dev(b), dev(np.zeros(63)))
+        assert e.value.status == fde.FDE_ENONFINITE
+
+
+def test_maxit_returns_notconv_with_info():
+    fde = need_gpu()
+    p = fi.variable_1d(n=255, alpha=1.2)
+    s = FDESystem.from_problem(p)
+    b = s.rhs(p.u0)
+    with fde.Plan(p, maxit=3) as plan:
+        x = dev(np.zeros(255))
+        info = plan.solve(dev(b), x, allow_notconv=True)
+        assert info.iters == 3 and not info.converged
+        xo, io = krylov.fgmres(s.matvec, b, pc.make("tau", s), restart=30, tol=1e-8, maxit=3)
+        assert relerr(host(x), xo) < 1e-10
+
+
+def test_coefficient_validation():
+    fde = need_gpu()
+    p = fi.variable_1d(n=63)
+    p.dplus = p.dplus.copy()
+    p.dplus[3] = -1.0
+    with pytest.raises(fde.FdeError) as e:
+        fde.Plan(p)
+    assert e.value.status == fde.FDE_EINVAL
+    p = fi.variable_1d(n=63)
+    p.dplus = np.zeros(63)
+    p.dminus = np.zeros(63)
+    with pytest.raises(fde.FdeError):
+        fde.Plan(p)
