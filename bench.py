@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Benchmark of the hot path on one MI355X.
+
+Workload (one bench step = one whole time-stepping job): the 2D
+variable-coefficient space-fractional diffusion problem on (0,2)^2 with
+alpha_x = 1.7, alpha_y = 1.4, n1 = n2 = 1023 (N = 1,046,529 unknowns),
+coefficients d+- = G(3-a)x^a(1+y) / G(3-a)(2-x)^a(1+y) and the matching
+y-direction fields, dt = h, u0 ~ U[-1,1] (seed 3), f = 0, 10 implicit-Euler
+steps; each step is the setup-free right-hand side b = nu u^{m-1} followed by a
+preconditioned FGMRES(30) solve with P_F to ||b - M u||/||b|| <= 1e-8 from
+x0 = u^{m-1}.  The plan is assembled inside each job (setup row of the path).
+Forms: all-float64 and mixed (float32 inner GMRES(k) with float32 matvec and
+tau solve inside the float64 outer FGMRES).
+
+Prints one JSON line.  value = linear solves (time steps) per second of the
+mixed form; the float64 form, time-to-tol per solve, iteration counts, the
+roofline of the dominant kernel (HIP events over the timed region, algorithmic
+bytes per launch), and the FP64 CPU oracle on a bounded sample are included.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed jobs per form")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1023)
+    ap.add_argument("--tsteps", type=int, default=10)
+    ap.add_argument("--inner", type=int, default=8)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--forms", default="fp64,mixed")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is a design "
+              "note, not a measured path", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import fde_inputs as fi
+    from paper_1912_13304_amd import fde
+
+    fde.load()
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    prob = fi.variable_2d(n=args.n, steps=args.tsteps)
+    N = prob.N
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev).reshape(-1).contiguous()
+    coef = [T(prob.dplus), T(prob.dminus), T(prob.eplus), T(prob.eminus)]
+    u0 = T(prob.u0)
+    forms = {"fp64": dict(precision=fde.FP64), "mixed": dict(precision=fde.MIXED, inner_steps=args.inner)}
+    forms = {k: v for k, v in forms.items() if k in args.forms.split(",")}
+
+    b = torch.empty(N, dtype=torch.float64, device=dev)
+    bufs = [torch.empty(N, dtype=torch.float64, device=dev) for _ in range(2)]
+
+    def job(kw, probe=fde.PROBE_OFF, keep_first=False):
+        params = fde.params_for(prob, **kw)
+        plan = fde.fde_assemble(params, *coef)
+        if probe:
+            fde.fde_probe(plan, probe)
+        u, x = bufs
+        u.copy_(u0)
+        infos = []
+        first = None
+        for m in range(args.tsteps):
+            fde.fde_rhs(plan, u, None, b)
+            x.copy_(u)   # x0 = u^{m-1}
+            infos.append(fde.fde_solve(plan, b, x).as_dict())
+            if keep_first and m == 0:
+                first = x.detach().cpu().numpy()
+            u, x = x, u
+        pr = fde.fde_probe_read(plan) if probe else None
+        fde.fde_destroy(plan)
+        return infos, pr, first
+
+    results = {}
+    dominant = {}
+    for name, kw in forms.items():
+        log(f"[bench] warmup {name} x{args.warmup}")
+        for _ in range(args.warmup):
+            job(kw)
+        # one untimed job per kernel class: share of GPU time per class
+        shares = {}
+        for cls_name, cls in (("maxpy64", fde.PROBE_MAXPY64), ("mdot64", fde.PROBE_MDOT64),
+                              ("line64", fde.PROBE_LINE64), ("line32", fde.PROBE_LINE32),
+                              ("maxpy32", fde.PROBE_MAXPY32), ("mdot32", fde.PROBE_MDOT32)):
+            _, pr, _ = job(kw, probe=cls)
+            ms, nl, by = pr
+            if nl:
+                shares[cls_name] = dict(ms=ms, launches=nl, bytes=by, GBps=by / (ms * 1e-3) / 1e9 if ms else 0.0,
+                                        cls=cls)
+        dom = max(shares, key=lambda k: shares[k]["ms"])
+        dominant[name] = dom
+        log(f"[bench] {name} kernel classes: " + ", ".join(f"{k}: {v['ms']:.2f} ms {v['GBps']:.0f} GB/s"
+                                                          for k, v in shares.items()))
+        # timed region: K whole jobs, the dominant kernel class probed with HIP events
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        all_infos = []
+        probe_tot = [0.0, 0, 0.0]
+        for _ in range(args.steps):
+            infos, pr, _ = job(kw, probe=shares[dom]["cls"])
+            all_infos.append(infos)
+            probe_tot = [probe_tot[0] + pr[0], probe_tot[1] + pr[1], probe_tot[2] + pr[2]]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        solves = args.steps * args.tsteps
+        its = [i["iters"] for inf in all_infos for i in inf]
+        results[name] = dict(
+            solves_per_s=solves / dt, ms_per_job=1e3 * dt / args.steps, ms_per_solve=1e3 * dt / solves,
+            iters_per_solve=float(np.mean(its)), iters_first_step=all_infos[0][0]["iters"],
+            inner_iters_per_solve=float(np.mean([i["inner_iters"] for inf in all_infos for i in inf])),
+            max_relres=float(max(i["relres_true"] for inf in all_infos for i in inf)),
+            all_converged=all(i["converged"] for inf in all_infos for i in inf),
+            kernel_classes={k: dict(ms_per_job=v["ms"], GBps=v["GBps"], launches=v["launches"])
+                            for k, v in shares.items()},
+            dominant=dict(cls=dom, ms=probe_tot[0], launches=probe_tot[1], bytes=probe_tot[2]),
+        )
+        log(f"[bench] {name}: {results[name]['solves_per_s']:.1f} solves/s, "
+            f"{results[name]['ms_per_solve']:.2f} ms/solve, {results[name]['iters_per_solve']:.1f} it/solve")
+
+    # plain copy bandwidth on the same GPU (1 GiB read + 1 GiB write)
+    src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 10 * 2 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+
+    head = "mixed" if "mixed" in results else "fp64"
+    d = results[head]["dominant"]
+    achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0
+    avg_us = 1e3 * d["ms"] / max(1, d["launches"])
+
+    # CPU oracle on a bounded sample: the first solve of the job
+    cpu = None
+    parity = None
+    if not args.no_cpu:
+        from oracle import krylov, precond as pc
+        from oracle.system import FDESystem
+        cores = min(16, len(os.sched_getaffinity(0)))
+        s = FDESystem.from_problem(prob, workers=cores)
+        P = pc.make("tau", s, workers=cores)
+        u0h = prob.u0.reshape(-1)
+        bh = s.rhs(u0h)
+        log(f"[bench] CPU oracle: first solve of the job on {cores} threads")
+        t0 = time.perf_counter()
+        xo, io = krylov.fgmres(s.matvec, bh, P, x0=u0h, restart=30, tol=prob.tol)
+        tc = time.perf_counter() - t0
+        cpu = {"value": 1.0 / tc, "unit": "solves/s", "cores": cores, "kind": "oracle",
+               "sample": f"first implicit-Euler solve of the job (1 of {args.tsteps}), FP64 FGMRES(30)+P_F "
+                         f"to 1e-8, {io['iters']} iterations, {tc:.1f} s"}
+        # parity of the same solve on the GPU (FP64 form)
+        _, _, first = job(forms.get("fp64", dict(precision=fde.FP64)), keep_first=True)
+        parity = {"fp64_first_solve_rel_diff": float(np.linalg.norm(first - xo) / np.linalg.norm(xo)),
+                  "oracle_iters": io["iters"]}
+        log(f"[bench] oracle {tc:.1f} s, parity {parity}")
+
+    out = {
+        "metric": "2D 1023^2 GMRES+P_Falpha time-to-tol & solves/s, mixed vs FP64; p99 served latency",
+        "value": results[head]["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": results[head]["ms_per_job"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32" if head == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"2D {args.n}x{args.n} variable-coefficient FDE, alpha=(1.7,1.4), dt=h, "
+                               f"{args.tsteps} implicit-Euler steps per job, FGMRES(30)+P_F to 1e-8, x0=u^(m-1)",
+                   "n": args.n, "N": N, "time_steps_per_job": args.tsteps, "restart": 30, "tol": prob.tol,
+                   "inner_steps": args.inner},
+        "forms": results,
+        "time_to_tol_ms": {k: v["ms_per_solve"] for k, v in results.items()},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": d["cls"],
+                     "avg_launch_us": avg_us, "copy_GBps": copy_gbs},
+        "cpu_baseline": cpu,
+        "parity": parity,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

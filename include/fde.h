@@ -148,6 +148,23 @@ size_t fde_plan_bytes(const fde_params* p);
 /* Releases the plan (synchronises the device first). NULL is ignored. */
 void fde_destroy(fde_plan plan);
 
+/* Kernel timing probe (benchmarking).  fde_probe(plan, cls) starts bracketing
+   every launch of one kernel class issued by this plan with HIP events on the
+   launch stream, and accumulates the launch's algorithmic bytes (each vector
+   operand read or written once); cls = FDE_PROBE_OFF stops.  fde_probe_read
+   synchronises on the recorded events and returns the summed kernel time in
+   milliseconds, the number of launches and the summed algorithmic bytes, then
+   clears the record.  Either pointer argument may be NULL. */
+enum { FDE_PROBE_OFF = 0,
+       FDE_PROBE_MAXPY64 = 1,   /* float64 multi-vector update w -= sum c_i V_i (Gram-Schmidt) */
+       FDE_PROBE_MDOT64 = 2,    /* float64 multi-dot V^T w                                       */
+       FDE_PROBE_LINE64 = 3,    /* float64 line transforms (DST-I / Toeplitz passes)            */
+       FDE_PROBE_LINE32 = 4,    /* float32 line transforms                                       */
+       FDE_PROBE_MAXPY32 = 5,
+       FDE_PROBE_MDOT32 = 6 };
+fde_status fde_probe(fde_plan plan, int cls);
+fde_status fde_probe_read(fde_plan plan, double* ms, long long* launches, double* bytes);
+
 /* Thread-local description of the last error, "" when none. */
 const char* fde_last_error(void);
 

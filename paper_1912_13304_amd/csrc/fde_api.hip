@@ -86,6 +86,11 @@ struct fde_plan_s {
   double* hstat_dev = nullptr;  // its device address
   KState* hks = nullptr;        // pinned host copy of the state header
   hipEvent_t ev[4] = {};
+  // timing probe
+  int probe = FDE_PROBE_OFF;
+  std::vector<hipEvent_t> pev;      // event pool, pairs (start, stop)
+  size_t pused = 0;                 // pairs recorded since the last read
+  double pbytes = 0.0;
   std::vector<void*> allocs;
   size_t bytes = 0;
 };
@@ -310,6 +315,7 @@ static fde_status direction_tables(fde_plan pl, double alpha, int n, cx<double>*
 static void destroy_impl(fde_plan pl) {
   if (!pl) return;
   (void)hipDeviceSynchronize();
+  for (auto& e : pl->pev) (void)hipEventDestroy(e);
   for (void* q : pl->allocs) (void)hipFree(q);
   if (pl->hstat) (void)hipHostFree(pl->hstat);
   if (pl->hks) (void)hipHostFree(pl->hks);
@@ -526,8 +532,68 @@ extern "C" fde_status fde_assemble(const fde_params* p, const double* dplus, con
 }
 
 // ---------------------------------------------------------------------------
+// Timing probe
+// ---------------------------------------------------------------------------
+struct ProbeScope {
+  fde_plan pl;
+  hipStream_t st;
+  bool on;
+  ProbeScope(fde_plan p, int cls, hipStream_t s, double bytes) : pl(p), st(s), on(p->probe == cls && cls != 0) {
+    if (!on) return;
+    if (pl->pev.size() < 2 * (pl->pused + 1)) {
+      for (int i = 0; i < 2; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) {
+          on = false;
+          return;
+        }
+        pl->pev.push_back(e);
+      }
+    }
+    (void)hipEventRecord(pl->pev[2 * pl->pused], st);
+    pl->pbytes += bytes;
+  }
+  ~ProbeScope() {
+    if (!on) return;
+    (void)hipEventRecord(pl->pev[2 * pl->pused + 1], st);
+    ++pl->pused;
+  }
+};
+
+extern "C" fde_status fde_probe(fde_plan pl, int cls) {
+  if (!pl) return fail(FDE_EINVAL, "NULL plan");
+  if (cls < FDE_PROBE_OFF || cls > FDE_PROBE_MDOT32) return fail(FDE_EINVAL, "bad probe class %d", cls);
+  pl->probe = cls;
+  return FDE_OK;
+}
+
+extern "C" fde_status fde_probe_read(fde_plan pl, double* ms, long long* launches, double* bytes) {
+  if (!pl) return fail(FDE_EINVAL, "NULL plan");
+  double tot = 0.0;
+  if (pl->pused) HIPCHK(hipEventSynchronize(pl->pev[2 * pl->pused - 1]));
+  for (size_t i = 0; i < pl->pused; ++i) {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, pl->pev[2 * i], pl->pev[2 * i + 1]));
+    tot += t;
+  }
+  if (ms) *ms = tot;
+  if (launches) *launches = (long long)pl->pused;
+  if (bytes) *bytes = pl->pbytes;
+  pl->pused = 0;
+  pl->pbytes = 0.0;
+  return FDE_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Launch helpers
 // ---------------------------------------------------------------------------
+static thread_local fde_plan g_probe_plan = nullptr;   // plan whose launches are being issued
+
+struct ProbePlanScope {
+  explicit ProbePlanScope(fde_plan pl) { g_probe_plan = pl; }
+  ~ProbePlanScope() { g_probe_plan = nullptr; }
+};
+
 template <typename T, bool COLS, int FL>
 static void launch_line(const Dir& d, LineArgs<T> a, hipStream_t st) {
   a.n = d.n;
@@ -549,7 +615,16 @@ static void launch_line(const Dir& d, LineArgs<T> a, hipStream_t st) {
     attr_set = true;
   }
   const int grid = 8 * ((a.ntiles + 7) / 8);
-  hipLaunchKernelGGL((line_kernel<T, COLS, FL>), dim3(grid), dim3(std::max(nth, 1)), lds, st, a);
+  // algorithmic bytes: every vector operand read or written once
+  const int nvec = (a.in != nullptr) + (a.pre != nullptr) + (a.post != nullptr) + (a.zout != nullptr) +
+                   ((FL & LF_TOEP) ? 2 : 0) + ((FL & LF_EXTBASE) ? 1 : 0) + 1;
+  const double bytes = (double)nvec * (double)d.n * (double)d.nlines * sizeof(T);
+  if (g_probe_plan) {
+    ProbeScope ps(g_probe_plan, sizeof(T) == 8 ? FDE_PROBE_LINE64 : FDE_PROBE_LINE32, st, bytes);
+    hipLaunchKernelGGL((line_kernel<T, COLS, FL>), dim3(grid), dim3(std::max(nth, 1)), lds, st, a);
+  } else {
+    hipLaunchKernelGGL((line_kernel<T, COLS, FL>), dim3(grid), dim3(std::max(nth, 1)), lds, st, a);
+  }
 }
 
 static int red_grid(long N) {
@@ -740,6 +815,7 @@ static void matvec_only(fde_plan pl, const T* x, T* y, T* t3, T bscale, T tscale
 
 extern "C" fde_status fde_matvec(fde_plan pl, const double* x, double* y, void* stream) {
   if (!pl || !x || !y) return fail(FDE_EINVAL, "NULL argument");
+  ProbePlanScope pps(pl);
   matvec_only<double>(pl, x, y, pl->t3, pl->nu, 1.0, (hipStream_t)stream, nullptr);
   HIPCHK(hipGetLastError());
   return FDE_OK;
@@ -747,6 +823,7 @@ extern "C" fde_status fde_matvec(fde_plan pl, const double* x, double* y, void* 
 
 extern "C" fde_status fde_tau_apply(fde_plan pl, const double* v, double* z, void* stream) {
   if (!pl || !v || !z) return fail(FDE_EINVAL, "NULL argument");
+  ProbePlanScope pps(pl);
   tau_only<double>(pl, v, nullptr, z, pl->t1, pl->t2, (hipStream_t)stream, nullptr);
   HIPCHK(hipGetLastError());
   return FDE_OK;
@@ -754,6 +831,7 @@ extern "C" fde_status fde_tau_apply(fde_plan pl, const double* v, double* z, voi
 
 extern "C" fde_status fde_rhs(fde_plan pl, const double* u, const double* f, double* b, void* stream) {
   if (!pl || !u || !b) return fail(FDE_EINVAL, "NULL argument");
+  ProbePlanScope pps(pl);
   hipStream_t st = (hipStream_t)stream;
   const long N = pl->N;
   if (pl->p.time == FDE_T_EULER) {
@@ -794,6 +872,7 @@ __global__ void ks_settol_kernel(KState* ks) {
 template <typename T>
 static void mdot(fde_plan pl, const T* V, long ldv, int k, const T* w, KState* ks, int mode, hipStream_t st,
                  const int* skip, const int* skip2) {
+  ProbeScope ps(pl, sizeof(T) == 8 ? FDE_PROBE_MDOT64 : FDE_PROBE_MDOT32, st, (double)(k + 1) * pl->N * sizeof(T));
   hipLaunchKernelGGL((mdot_kernel<T>), dim3(red_grid(pl->N)), dim3(RED_THREADS), 0, st, V, ldv, k, w, pl->N,
                      pl->part, ks, mode, skip, skip2);
 }
@@ -801,6 +880,7 @@ static void mdot(fde_plan pl, const T* V, long ldv, int k, const T* w, KState* k
 template <typename T>
 static void maxpy(fde_plan pl, const T* V, long ldv, int k, T* w, int cmode, KState* ks, int emode, int col,
                   double* hstat, hipStream_t st, const int* skip, const int* skip2) {
+  ProbeScope ps(pl, sizeof(T) == 8 ? FDE_PROBE_MAXPY64 : FDE_PROBE_MAXPY32, st, (double)(k + 2) * pl->N * sizeof(T));
   hipLaunchKernelGGL((maxpy_kernel<T>), dim3(red_grid(pl->N)), dim3(RED_THREADS), 0, st, V, ldv, k, w, w, pl->N,
                      cmode, pl->part, ks, emode, col, hstat, skip, skip2);
 }
@@ -1003,6 +1083,7 @@ static fde_status solve_pcg(fde_plan pl, const double* b, double* x, fde_info* i
 
 extern "C" fde_status fde_solve(fde_plan pl, const double* b, double* x, fde_info* info, void* stream) {
   if (!pl || !b || !x) return fail(FDE_EINVAL, "NULL argument");
+  ProbePlanScope pps(pl);
   auto t0 = std::chrono::steady_clock::now();
   fde_status s = pl->p.solver == FDE_S_PCG ? solve_pcg(pl, b, x, info, (hipStream_t)stream)
                                            : solve_gmres(pl, b, x, info, (hipStream_t)stream);

@@ -25,8 +25,10 @@ D_LEFT, D_RIGHT = 0, 1
 S_GMRES, S_PCG = 0, 1
 FP64, MIXED = 0, 1
 
+PROBE_OFF, PROBE_MAXPY64, PROBE_MDOT64, PROBE_LINE64, PROBE_LINE32, PROBE_MAXPY32, PROBE_MDOT32 = range(7)
+
 EXPORTED = ["fde_default_params", "fde_assemble", "fde_matvec", "fde_tau_apply", "fde_solve", "fde_rhs",
-            "fde_plan_bytes", "fde_destroy", "fde_last_error"]
+            "fde_plan_bytes", "fde_destroy", "fde_last_error", "fde_probe", "fde_probe_read"]
 
 
 class FdeParams(ctypes.Structure):
@@ -100,6 +102,11 @@ def load(path: str = LIB_PATH):
     lib.fde_plan_bytes.restype = ctypes.c_size_t
     lib.fde_destroy.argtypes = [vp]
     lib.fde_destroy.restype = None
+    lib.fde_probe.argtypes = [vp, ctypes.c_int]
+    lib.fde_probe.restype = ctypes.c_int
+    lib.fde_probe_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong),
+                                   ctypes.POINTER(ctypes.c_double)]
+    lib.fde_probe_read.restype = ctypes.c_int
     lib.fde_last_error.argtypes = []
     lib.fde_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -196,6 +203,17 @@ def fde_plan_bytes(params: FdeParams) -> int:
 def fde_destroy(plan):
     if plan:
         load().fde_destroy(plan)
+
+
+def fde_probe(plan, cls):
+    return _check(load().fde_probe(plan, int(cls)))
+
+
+def fde_probe_read(plan):
+    """(milliseconds, launches, algorithmic bytes) accumulated since the last read."""
+    ms, n, by = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double()
+    _check(load().fde_probe_read(plan, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)))
+    return ms.value, n.value, by.value
 
 
 class Plan:
