@@ -87,7 +87,7 @@ typedef struct {
                           Section 3.1 Case I: nu/c when all coefficients equal one constant c,
                           0 otherwise                                                             */
   int    solver;       /* FDE_S_*                                                                  */
-  int    restart;      /* GMRES cycle length m, 1..64                                              */
+  int    restart;      /* GMRES cycle length m, 1..32                                              */
   int    maxit;        /* cap on the total number of (outer) iterations                           */
   double tol;          /* stop when ||b - M x||_2 <= tol ||b||_2                                   */
   int    precision;    /* FDE_FP64 | FDE_MIXED                                                     */

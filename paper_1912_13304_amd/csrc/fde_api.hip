@@ -62,6 +62,7 @@ struct Dir {
 template <typename T>
 struct Consts {
   T *dp = nullptr, *dm = nullptr, *ep = nullptr, *em = nullptr;  // coefficients
+  T *ept = nullptr, *emt = nullptr;                              // e+- transposed (n1 x n2)
   T* dinv = nullptr;                                             // D^{-1} (null: no D factor)
   T *fx = nullptr, *fy = nullptr, *fzero = nullptr;              // symbol samples
   cx<T> *W2x = nullptr, *W2y = nullptr, *lamx = nullptr, *lamy = nullptr;
@@ -74,13 +75,15 @@ struct fde_plan_s {
   double hx = 0, hy = 0, hxa = 0, nu = 0, kappa = 0, shift = 0;
   bool has_dinv = false;
   int dside = FDE_D_LEFT;
-  Dir rows, cols;
+  Dir rows, trows;   // lines along x (rows of the (n2, n1) array); along y (rows of its transpose)
   Consts<double> c64;
   Consts<float> c32;
   int m = 30, kin = 0;
   double *V = nullptr, *Z = nullptr, *t1 = nullptr, *t2 = nullptr, *t3 = nullptr;
   float *Vf = nullptr, *t1f = nullptr, *t2f = nullptr, *t3f = nullptr, *uf = nullptr, *zf = nullptr;
+  template <typename T> T* tmp(int i);
   double* part = nullptr;
+  double* stats_buf = nullptr;   // 3 + 3*256 doubles for the setup statistics
   KState *ks = nullptr, *ksi = nullptr;
   double* hstat = nullptr;      // mapped pinned host memory
   double* hstat_dev = nullptr;  // its device address
@@ -95,6 +98,9 @@ struct fde_plan_s {
   size_t bytes = 0;
 };
 
+template <> double* fde_plan_s::tmp<double>(int i) { return i == 1 ? t1 : i == 2 ? t2 : t3; }
+template <> float* fde_plan_s::tmp<float>(int i) { return i == 1 ? t1f : i == 2 ? t2f : t3f; }
+
 static int ilog2(long v) {
   int l = 0;
   while ((1L << l) < v) ++l;
@@ -103,13 +109,12 @@ static int ilog2(long v) {
 
 static bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
 
-// Lines per workgroup for a transform of size P: B*P/8 threads per workgroup,
-// at most 1024; aim for 512 threads and enough workgroups to cover the chip.
+// Lines per workgroup for a transform of size P: B*P/8 threads per
+// workgroup.  One line per workgroup (at least one wavefront) lets several
+// workgroups share a CU, so that the load, transform and store phases of
+// different lines overlap.
 static void choose_tile(Dir& d) {
-  int B = std::max(1, 4096 / d.P);
-  // keep at least ~256 workgroups when there are enough lines
-  while (B > 1 && (d.nlines + B - 1) / B < 256 && B * d.P / 8 > 64) B >>= 1;
-  if (B * d.P / 8 > 1024) B = std::max(1, 8192 / d.P);
+  int B = std::max(1, 512 / d.P);
   d.B = B;
   d.logB = ilog2(B);
 }
@@ -161,7 +166,7 @@ static fde_status validate(const fde_params* p) {
   if (p->prec == FDE_P_TILDE && p->dim != 1) return fail(FDE_EINVAL, "P_tilde is defined in 1D only");
   if (p->dside != FDE_D_LEFT && p->dside != FDE_D_RIGHT) return fail(FDE_EINVAL, "bad dside");
   if (p->solver != FDE_S_GMRES && p->solver != FDE_S_PCG) return fail(FDE_EINVAL, "bad solver");
-  if (p->restart < 1 || p->restart > KMAX) return fail(FDE_EINVAL, "restart must be in 1..%d", KMAX);
+  if (p->restart < 1 || p->restart > 32) return fail(FDE_EINVAL, "restart must be in 1..32");
   if (p->maxit < 1) return fail(FDE_EINVAL, "maxit must be >= 1");
   if (p->precision != FDE_FP64 && p->precision != FDE_MIXED) return fail(FDE_EINVAL, "bad precision");
   if (p->precision == FDE_MIXED && (p->inner_steps < 0 || p->inner_steps > 32))
@@ -327,9 +332,10 @@ static void destroy_impl(fde_plan pl) {
 extern "C" void fde_destroy(fde_plan pl) { destroy_impl(pl); }
 
 static fde_status coef_stats(fde_plan pl, const double* a, double* st3, hipStream_t st) {
-  double* d = nullptr;
-  TRY(dalloc(pl, &d, 3));
-  hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(RED_THREADS), 0, st, a, pl->N, d);
+  double* d = pl->stats_buf;
+  const int G = 256;
+  hipLaunchKernelGGL(stats_part_kernel, dim3(G), dim3(RED_THREADS), 0, st, a, pl->N, d + 3);
+  hipLaunchKernelGGL(stats_final_kernel, dim3(1), dim3(64), 0, st, d + 3, G, d);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(st3, d, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -364,16 +370,17 @@ static fde_status assemble_impl(const fde_params* p, const double* dp, const dou
   pl->rows.es = 1;
   choose_tile(pl->rows);
   if (p->dim == 2) {
-    pl->cols.n = pl->n2;
-    pl->cols.P = pl->n2 + 1;
-    pl->cols.logP = ilog2(pl->cols.P);
-    pl->cols.nlines = pl->n1;
-    pl->cols.ls = 1;
-    pl->cols.es = pl->n1;
-    choose_tile(pl->cols);
+    pl->trows.n = pl->n2;
+    pl->trows.P = pl->n2 + 1;
+    pl->trows.logP = ilog2(pl->trows.P);
+    pl->trows.nlines = pl->n1;
+    pl->trows.ls = pl->n2;
+    pl->trows.es = 1;
+    choose_tile(pl->trows);
   }
 
   // coefficients: validate and copy
+  TRY(dalloc(pl, &pl->stats_buf, 3 + 3 * 256));
   const double* src[4] = {dp, dm, ep, em};
   const int ncoef = p->dim == 2 ? 4 : 2;
   double stats[4][3];
@@ -396,6 +403,22 @@ static fde_status assemble_impl(const fde_params* p, const double* dp, const dou
   pl->c64.dm = d64[1];
   pl->c64.ep = d64[2];
   pl->c64.em = d64[3];
+  if (p->dim == 2) {
+    TRY(dalloc(pl, &pl->c64.ept, N));
+    TRY(dalloc(pl, &pl->c64.emt, N));
+    TRY(dalloc(pl, &pl->c32.ept, N));
+    TRY(dalloc(pl, &pl->c32.emt, N));
+    const dim3 tg((pl->n1 + 31) / 32, (pl->n2 + 31) / 32);
+    hipLaunchKernelGGL((transpose_kernel<double, false>), tg, dim3(256), 0, st, d64[2], pl->c64.ept, pl->n2, pl->n1,
+                       (const double*)nullptr, (const int*)nullptr, (const int*)nullptr);
+    hipLaunchKernelGGL((transpose_kernel<double, false>), tg, dim3(256), 0, st, d64[3], pl->c64.emt, pl->n2, pl->n1,
+                       (const double*)nullptr, (const int*)nullptr, (const int*)nullptr);
+    hipLaunchKernelGGL((transpose_kernel<float, false>), tg, dim3(256), 0, st, d32[2], pl->c32.ept, pl->n2, pl->n1,
+                       (const float*)nullptr, (const int*)nullptr, (const int*)nullptr);
+    hipLaunchKernelGGL((transpose_kernel<float, false>), tg, dim3(256), 0, st, d32[3], pl->c32.emt, pl->n2, pl->n1,
+                       (const float*)nullptr, (const int*)nullptr, (const int*)nullptr);
+    HIPCHK(hipGetLastError());
+  }
   pl->c32.dp = d32[0];
   pl->c32.dm = d32[1];
   pl->c32.ep = d32[2];
@@ -538,7 +561,7 @@ struct ProbeScope {
   fde_plan pl;
   hipStream_t st;
   bool on;
-  ProbeScope(fde_plan p, int cls, hipStream_t s, double bytes) : pl(p), st(s), on(p->probe == cls && cls != 0) {
+  ProbeScope(fde_plan p, int cls, hipStream_t s, double bytes) : pl(p), st(s), on(p && p->probe == cls && cls != 0) {
     if (!on) return;
     if (pl->pev.size() < 2 * (pl->pused + 1)) {
       for (int i = 0; i < 2; ++i) {
@@ -594,7 +617,18 @@ struct ProbePlanScope {
   ~ProbePlanScope() { g_probe_plan = nullptr; }
 };
 
-template <typename T, bool COLS, int FL>
+template <typename T, int FL, int LOGP>
+static void launch_line_k(const Dir& d, const LineArgs<T>& a, int grid, int nth, size_t lds, hipStream_t st) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&line_kernel<T, false, FL, LOGP>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((line_kernel<T, false, FL, LOGP>), dim3(grid), dim3(nth), lds, st, a);
+}
+
+template <typename T, int FL>
 static void launch_line(const Dir& d, LineArgs<T> a, hipStream_t st) {
   a.n = d.n;
   a.P = d.P;
@@ -602,35 +636,34 @@ static void launch_line(const Dir& d, LineArgs<T> a, hipStream_t st) {
   a.nlines = d.nlines;
   a.B = d.B;
   a.logB = d.logB;
-  a.LS = d.P;
+  a.LS = line_stride(d.P);
   a.ls = d.ls;
   a.es = d.es;
   a.ntiles = (d.nlines + d.B - 1) / d.B;
-  const int nth = d.B * d.P / 8;
-  const size_t lds = ((size_t)d.B * a.LS + 2 * d.B) * sizeof(cx<T>);
-  static bool attr_set = false;
-  if (!attr_set) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&line_kernel<T, COLS, FL>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attr_set = true;
-  }
+  const int nth = std::max(1, d.B * d.P / 8);
+  const size_t lds = ((size_t)d.B * a.LS + 2 * d.B + (size_t)d.B * d.P) * sizeof(cx<T>);
   const int grid = 8 * ((a.ntiles + 7) / 8);
   // algorithmic bytes: every vector operand read or written once
   const int nvec = (a.in != nullptr) + (a.pre != nullptr) + (a.post != nullptr) + (a.zout != nullptr) +
                    ((FL & LF_TOEP) ? 2 : 0) + ((FL & LF_EXTBASE) ? 1 : 0) + 1;
   const double bytes = (double)nvec * (double)d.n * (double)d.nlines * sizeof(T);
-  if (g_probe_plan) {
-    ProbeScope ps(g_probe_plan, sizeof(T) == 8 ? FDE_PROBE_LINE64 : FDE_PROBE_LINE32, st, bytes);
-    hipLaunchKernelGGL((line_kernel<T, COLS, FL>), dim3(grid), dim3(std::max(nth, 1)), lds, st, a);
-  } else {
-    hipLaunchKernelGGL((line_kernel<T, COLS, FL>), dim3(grid), dim3(std::max(nth, 1)), lds, st, a);
+  ProbeScope ps(g_probe_plan ? g_probe_plan : nullptr, sizeof(T) == 8 ? FDE_PROBE_LINE64 : FDE_PROBE_LINE32, st,
+                bytes);
+  switch (d.logP) {
+    case 3: launch_line_k<T, FL, 3>(d, a, grid, nth, lds, st); break;
+    case 4: launch_line_k<T, FL, 4>(d, a, grid, nth, lds, st); break;
+    case 5: launch_line_k<T, FL, 5>(d, a, grid, nth, lds, st); break;
+    case 6: launch_line_k<T, FL, 6>(d, a, grid, nth, lds, st); break;
+    case 7: launch_line_k<T, FL, 7>(d, a, grid, nth, lds, st); break;
+    case 8: launch_line_k<T, FL, 8>(d, a, grid, nth, lds, st); break;
+    case 9: launch_line_k<T, FL, 9>(d, a, grid, nth, lds, st); break;
+    case 10: launch_line_k<T, FL, 10>(d, a, grid, nth, lds, st); break;
+    case 11: launch_line_k<T, FL, 11>(d, a, grid, nth, lds, st); break;
+    case 12: launch_line_k<T, FL, 12>(d, a, grid, nth, lds, st); break;
+    default: launch_line_k<T, FL, 0>(d, a, grid, nth, lds, st); break;
   }
 }
 
-static int red_grid(long N) {
-  long g = (N + (long)RED_THREADS * RED_EPT - 1) / ((long)RED_THREADS * RED_EPT);
-  return (int)std::max(1L, std::min<long>(RED_MAXG, g));
-}
 static int ew_grid(long N) { return (int)std::max(1L, std::min<long>(2048, (N + 255) / 256)); }
 
 template <typename T>
@@ -640,31 +673,61 @@ const Consts<double>& consts<double>(fde_plan pl) { return pl->c64; }
 template <>
 const Consts<float>& consts<float>(fde_plan pl) { return pl->c32; }
 
-// Toeplitz-type LineArgs for one direction.
+// Toeplitz-type LineArgs.  ydir: lines along y, i.e. rows of the transposed
+// (n1, n2) array, with the transposed e+- coefficients.
 template <typename T>
-static LineArgs<T> toep_args(fde_plan pl, bool ydir, const int* skip) {
+static LineArgs<T> toep_args(fde_plan pl, bool ydir, const int* skip, const int* skip2) {
   const Consts<T>& c = consts<T>(pl);
   LineArgs<T> a{};
   a.W2 = ydir ? c.W2y : c.W2x;
   a.lam = ydir ? c.lamy : c.lamx;
-  a.cplus = ydir ? c.ep : c.dp;
-  a.cminus = ydir ? c.em : c.dm;
+  a.cplus = ydir ? c.ept : c.dp;
+  a.cminus = ydir ? c.emt : c.dm;
   a.skip = skip;
+  a.skip2 = skip2;
   return a;
 }
 
-// w = M v with v's DST-side factors: the general fused step used by the
-// solvers.  Computes z = P^{-1}(sc * v) (stored in z when z != null) and
-// w = M z.  With prec NONE, z = sc * v.
+// out (cols x rows) = in^T (+ addend)
 template <typename T>
-static void tau_matvec(fde_plan pl, const T* v, const double* sc, T* z, T* w, T* t1, T* t2, T* t3,
-                       hipStream_t st, const int* skip) {
+static void transpose(fde_plan pl, const T* in, T* out, int rows, int cols, const T* addend, hipStream_t st,
+                      const int* skip, const int* skip2) {
+  const dim3 g((cols + 31) / 32, (rows + 31) / 32);
+  if (addend)
+    hipLaunchKernelGGL((transpose_kernel<T, true>), g, dim3(256), 0, st, in, out, rows, cols, addend, skip, skip2);
+  else
+    hipLaunchKernelGGL((transpose_kernel<T, false>), g, dim3(256), 0, st, in, out, rows, cols, addend, skip, skip2);
+}
+
+// y-direction part added to an x-direction part: y = xpart + tscale * kappa *
+// (E+ (T_y (x) I) + E- (T_y^T (x) I)) x, computed on the transpose of x.
+template <typename T>
+static void add_y_part(fde_plan pl, const T* x, const T* xpart, T* y, T tscale, hipStream_t st, const int* skip,
+                       const int* skip2) {
+  T* xt = pl->tmp<T>(1);
+  T* yt = pl->tmp<T>(2);
+  transpose<T>(pl, x, xt, pl->n2, pl->n1, nullptr, st, skip, skip2);
+  LineArgs<T> q = toep_args<T>(pl, true, skip, skip2);
+  q.in = xt;
+  q.bscale = T(0);
+  q.tscale = tscale * (T)pl->kappa;
+  q.out = yt;
+  launch_line<T, LF_TOEP>(pl->trows, q, st);
+  transpose<T>(pl, yt, y, pl->n1, pl->n2, xpart, st, skip, skip2);
+}
+
+// z = P^{-1}(sc * v) (stored when z != null; the DST-side factors D^{-1} as
+// dside says) and w = M z: the fused operator step of the solvers.  With
+// prec NONE, z = sc * v.
+template <typename T>
+static void tau_matvec(fde_plan pl, const T* v, const double* sc, T* z, T* w, hipStream_t st, const int* skip,
+                       const int* skip2) {
   const Consts<T>& c = consts<T>(pl);
   const bool tau = pl->p.prec != FDE_P_NONE;
   const T* pre = (pl->has_dinv && pl->dside == FDE_D_LEFT) ? c.dinv : nullptr;
   const T* post = (pl->has_dinv && pl->dside == FDE_D_RIGHT) ? c.dinv : nullptr;
   if (pl->dim == 1) {
-    LineArgs<T> a = toep_args<T>(pl, false, skip);
+    LineArgs<T> a = toep_args<T>(pl, false, skip, skip2);
     a.in = v;
     a.sc = sc;
     a.pre = pre;
@@ -676,17 +739,20 @@ static void tau_matvec(fde_plan pl, const T* v, const double* sc, T* z, T* w, T*
     a.tscale = T(1);
     a.out = w;
     if (tau) {
-      if (z) launch_line<T, false, LF_DST1 | LF_FDST2 | LF_STOREZ | LF_TOEP>(pl->rows, a, st);
-      else launch_line<T, false, LF_DST1 | LF_FDST2 | LF_TOEP>(pl->rows, a, st);
+      if (z) launch_line<T, LF_DST1 | LF_FDST2 | LF_STOREZ | LF_TOEP>(pl->rows, a, st);
+      else launch_line<T, LF_DST1 | LF_FDST2 | LF_TOEP>(pl->rows, a, st);
     } else {
-      if (z) launch_line<T, false, LF_STOREZ | LF_TOEP>(pl->rows, a, st);
-      else launch_line<T, false, LF_TOEP>(pl->rows, a, st);
+      if (z) launch_line<T, LF_STOREZ | LF_TOEP>(pl->rows, a, st);
+      else launch_line<T, LF_TOEP>(pl->rows, a, st);
     }
     return;
   }
-  T* zz = z ? z : t1;   // the column pass needs z in memory
+  T* t1 = pl->tmp<T>(1);
+  T* t2 = pl->tmp<T>(2);
+  T* t3 = pl->tmp<T>(3);
+  T* zz = z;   // 2D callers always pass z: the y-direction pass reads it
   if (tau) {
-    // rows: DST (with D^{-1} in front for the D tau order)
+    // rows: DST along x (D^{-1} first for the D tau order)
     LineArgs<T> a{};
     a.in = v;
     a.sc = sc;
@@ -694,50 +760,46 @@ static void tau_matvec(fde_plan pl, const T* v, const double* sc, T* z, T* w, T*
     a.W2 = c.W2x;
     a.out = t1;
     a.skip = skip;
-    launch_line<T, false, LF_DST1>(pl->rows, a, st);
-    // columns: DST, divide by F, DST
+    a.skip2 = skip2;
+    launch_line<T, LF_DST1>(pl->rows, a, st);
+    // along y on the transpose: DST, divide by F, DST
+    transpose<T>(pl, t1, t2, pl->n2, pl->n1, nullptr, st, skip, skip2);
     LineArgs<T> b{};
-    b.in = t1;
+    b.in = t2;
     b.fline = c.fx;
     b.felem = c.fy;
     b.W2 = c.W2y;
-    b.out = t2;
+    b.out = t1;
     b.skip = skip;
-    launch_line<T, true, LF_DST1 | LF_FDST2>(pl->cols, b, st);
-    // rows: DST (D^{-1} after for tau D), store z, x-direction Toeplitz
-    LineArgs<T> r = toep_args<T>(pl, false, skip);
+    b.skip2 = skip2;
+    launch_line<T, LF_DST1 | LF_FDST2>(pl->trows, b, st);
+    transpose<T>(pl, t1, t2, pl->n1, pl->n2, nullptr, st, skip, skip2);
+    // rows: DST along x (D^{-1} after for tau D), store z, x-direction Toeplitz
+    LineArgs<T> r = toep_args<T>(pl, false, skip, skip2);
     r.in = t2;
     r.post = post;
     r.zout = zz;
-    r.W2 = c.W2x;
     r.bscale = (T)pl->nu;
     r.tscale = T(1);
     r.out = t3;
-    launch_line<T, false, LF_DST1 | LF_STOREZ | LF_TOEP>(pl->rows, r, st);
+    launch_line<T, LF_DST1 | LF_STOREZ | LF_TOEP>(pl->rows, r, st);
   } else {
-    LineArgs<T> r = toep_args<T>(pl, false, skip);
+    LineArgs<T> r = toep_args<T>(pl, false, skip, skip2);
     r.in = v;
     r.sc = sc;
     r.zout = zz;
     r.bscale = (T)pl->nu;
     r.tscale = T(1);
     r.out = t3;
-    launch_line<T, false, LF_STOREZ | LF_TOEP>(pl->rows, r, st);
+    launch_line<T, LF_STOREZ | LF_TOEP>(pl->rows, r, st);
   }
-  // columns: y-direction Toeplitz added to the x part
-  LineArgs<T> q = toep_args<T>(pl, true, skip);
-  q.in = zz;
-  q.base = t3;
-  q.bscale = T(1);
-  q.tscale = (T)pl->kappa;
-  q.out = w;
-  launch_line<T, true, LF_TOEP | LF_EXTBASE>(pl->cols, q, st);
+  add_y_part<T>(pl, zz, t3, w, T(1), st, skip, skip2);
 }
 
 // z = P^{-1}(sc * v)
 template <typename T>
-static void tau_only(fde_plan pl, const T* v, const double* sc, T* z, T* t1, T* t2, hipStream_t st,
-                     const int* skip, const int* skip2 = nullptr) {
+static void tau_only(fde_plan pl, const T* v, const double* sc, T* z, hipStream_t st, const int* skip,
+                     const int* skip2 = nullptr) {
   const Consts<T>& c = consts<T>(pl);
   const T* pre = (pl->has_dinv && pl->dside == FDE_D_LEFT) ? c.dinv : nullptr;
   const T* post = (pl->has_dinv && pl->dside == FDE_D_RIGHT) ? c.dinv : nullptr;
@@ -757,9 +819,12 @@ static void tau_only(fde_plan pl, const T* v, const double* sc, T* z, T* t1, T* 
     a.W2 = c.W2x;
     a.out = z;
     a.skip = skip;
-    launch_line<T, false, LF_DST1 | LF_FDST2>(pl->rows, a, st);
+    a.skip2 = skip2;
+    launch_line<T, LF_DST1 | LF_FDST2>(pl->rows, a, st);
     return;
   }
+  T* t1 = pl->tmp<T>(1);
+  T* t2 = pl->tmp<T>(2);
   LineArgs<T> a{};
   a.in = v;
   a.sc = sc;
@@ -767,56 +832,52 @@ static void tau_only(fde_plan pl, const T* v, const double* sc, T* z, T* t1, T* 
   a.W2 = c.W2x;
   a.out = t1;
   a.skip = skip;
-  launch_line<T, false, LF_DST1>(pl->rows, a, st);
+  a.skip2 = skip2;
+  launch_line<T, LF_DST1>(pl->rows, a, st);
+  transpose<T>(pl, t1, t2, pl->n2, pl->n1, nullptr, st, skip, skip2);
   LineArgs<T> b{};
-  b.in = t1;
+  b.in = t2;
   b.fline = c.fx;
   b.felem = c.fy;
   b.W2 = c.W2y;
-  b.out = t2;
+  b.out = t1;
   b.skip = skip;
-  launch_line<T, true, LF_DST1 | LF_FDST2>(pl->cols, b, st);
+  b.skip2 = skip2;
+  launch_line<T, LF_DST1 | LF_FDST2>(pl->trows, b, st);
+  transpose<T>(pl, t1, t2, pl->n1, pl->n2, nullptr, st, skip, skip2);
   LineArgs<T> r{};
   r.in = t2;
   r.post = post;
   r.W2 = c.W2x;
   r.out = z;
   r.skip = skip;
-  launch_line<T, false, LF_DST1>(pl->rows, r, st);
+  r.skip2 = skip2;
+  launch_line<T, LF_DST1>(pl->rows, r, st);
 }
 
-// y = bscale*x + tscale*(A_x x) + tscale*kappa*(A_y x)   (bscale = nu, tscale = 1: y = M x)
+// y = bscale*x + tscale*(A_x x + kappa A_y x)   (bscale = nu, tscale = 1: y = M x)
 template <typename T>
-static void matvec_only(fde_plan pl, const T* x, T* y, T* t3, T bscale, T tscale, hipStream_t st,
-                        const int* skip) {
-  if (pl->dim == 1) {
-    LineArgs<T> a = toep_args<T>(pl, false, skip);
-    a.in = x;
-    a.bscale = bscale;
-    a.tscale = tscale;
-    a.out = y;
-    launch_line<T, false, LF_TOEP>(pl->rows, a, st);
-    return;
-  }
-  LineArgs<T> a = toep_args<T>(pl, false, skip);
+static void matvec_only(fde_plan pl, const T* x, T* y, T bscale, T tscale, hipStream_t st, const int* skip,
+                        const int* skip2 = nullptr) {
+  LineArgs<T> a = toep_args<T>(pl, false, skip, skip2);
   a.in = x;
   a.bscale = bscale;
   a.tscale = tscale;
+  if (pl->dim == 1) {
+    a.out = y;
+    launch_line<T, LF_TOEP>(pl->rows, a, st);
+    return;
+  }
+  T* t3 = pl->tmp<T>(3);
   a.out = t3;
-  launch_line<T, false, LF_TOEP>(pl->rows, a, st);
-  LineArgs<T> q = toep_args<T>(pl, true, skip);
-  q.in = x;
-  q.base = t3;
-  q.bscale = T(1);
-  q.tscale = tscale * (T)pl->kappa;
-  q.out = y;
-  launch_line<T, true, LF_TOEP | LF_EXTBASE>(pl->cols, q, st);
+  launch_line<T, LF_TOEP>(pl->rows, a, st);
+  add_y_part<T>(pl, x, t3, y, tscale, st, skip, skip2);
 }
 
 extern "C" fde_status fde_matvec(fde_plan pl, const double* x, double* y, void* stream) {
   if (!pl || !x || !y) return fail(FDE_EINVAL, "NULL argument");
   ProbePlanScope pps(pl);
-  matvec_only<double>(pl, x, y, pl->t3, pl->nu, 1.0, (hipStream_t)stream, nullptr);
+  matvec_only<double>(pl, x, y, pl->nu, 1.0, (hipStream_t)stream, nullptr);
   HIPCHK(hipGetLastError());
   return FDE_OK;
 }
@@ -824,7 +885,7 @@ extern "C" fde_status fde_matvec(fde_plan pl, const double* x, double* y, void* 
 extern "C" fde_status fde_tau_apply(fde_plan pl, const double* v, double* z, void* stream) {
   if (!pl || !v || !z) return fail(FDE_EINVAL, "NULL argument");
   ProbePlanScope pps(pl);
-  tau_only<double>(pl, v, nullptr, z, pl->t1, pl->t2, (hipStream_t)stream, nullptr);
+  tau_only<double>(pl, v, nullptr, z, (hipStream_t)stream, nullptr);
   HIPCHK(hipGetLastError());
   return FDE_OK;
 }
@@ -837,7 +898,7 @@ extern "C" fde_status fde_rhs(fde_plan pl, const double* u, const double* f, dou
   if (pl->p.time == FDE_T_EULER) {
     hipLaunchKernelGGL(axpby_kernel, dim3(ew_grid(N)), dim3(256), 0, st, pl->nu, u, pl->hxa, f, b, N);
   } else {
-    matvec_only<double>(pl, u, b, pl->t3, pl->nu, -1.0, st, nullptr);
+    matvec_only<double>(pl, u, b, pl->nu, -1.0, st, nullptr);
     if (f) hipLaunchKernelGGL(axpby_kernel, dim3(ew_grid(N)), dim3(256), 0, st, 1.0, b, 2.0 * pl->hxa, f, b, N);
   }
   HIPCHK(hipGetLastError());
@@ -861,7 +922,6 @@ __global__ void ks_init_kernel(KState* ks, int maxit, int m, double tol) {
   ks->tolabs = tol;   // multiplied by ||b|| once it is known
   ks->beta = ks->est = ks->hn = 0;
   ks->rz = ks->pq = ks->alpha = ks->betacg = 0;
-  ks->counter = 0;
   for (int i = 0; i <= KMAX; ++i) ks->scale[i] = 0.0;
 }
 
@@ -869,32 +929,72 @@ __global__ void ks_settol_kernel(KState* ks) {
   if (threadIdx.x == 0) ks->tolabs = ks->tolabs * ks->bnorm;
 }
 
-template <typename T>
-static void mdot(fde_plan pl, const T* V, long ldv, int k, const T* w, KState* ks, int mode, hipStream_t st,
-                 const int* skip, const int* skip2) {
-  ProbeScope ps(pl, sizeof(T) == 8 ? FDE_PROBE_MDOT64 : FDE_PROBE_MDOT32, st, (double)(k + 1) * pl->N * sizeof(T));
-  hipLaunchKernelGGL((mdot_kernel<T>), dim3(red_grid(pl->N)), dim3(RED_THREADS), 0, st, V, ldv, k, w, pl->N,
-                     pl->part, ks, mode, skip, skip2);
+static int red_grid(long N, long per) {
+  return (int)std::max(1L, std::min<long>(RED_MAXG, (N + per - 1) / per));
 }
 
+static void finalize(fde_plan pl, int G, int nq, KState* ks, int fkind, int emode, int col, double* hstat,
+                     hipStream_t st, const int* skip, const int* skip2) {
+  if (G <= 1) return;
+  if (nq <= 1)
+    hipLaunchKernelGGL(finalize_kernel<1>, dim3(1), dim3(RED_THREADS), 0, st, pl->part, G, nq, ks, fkind, emode,
+                       col, hstat, skip, skip2);
+  else if (nq <= 8)
+    hipLaunchKernelGGL(finalize_kernel<8>, dim3(1), dim3(RED_THREADS), 0, st, pl->part, G, nq, ks, fkind, emode,
+                       col, hstat, skip, skip2);
+  else if (nq <= 16)
+    hipLaunchKernelGGL(finalize_kernel<16>, dim3(1), dim3(RED_THREADS), 0, st, pl->part, G, nq, ks, fkind, emode,
+                       col, hstat, skip, skip2);
+  else
+    hipLaunchKernelGGL(finalize_kernel<32>, dim3(1), dim3(RED_THREADS), 0, st, pl->part, G, nq, ks, fkind, emode,
+                       col, hstat, skip, skip2);
+}
+
+// ||a - b||^2 with an epilogue; out = a - b when out != null.
 template <typename T>
-static void maxpy(fde_plan pl, const T* V, long ldv, int k, T* w, int cmode, KState* ks, int emode, int col,
-                  double* hstat, hipStream_t st, const int* skip, const int* skip2) {
-  ProbeScope ps(pl, sizeof(T) == 8 ? FDE_PROBE_MAXPY64 : FDE_PROBE_MAXPY32, st, (double)(k + 2) * pl->N * sizeof(T));
-  hipLaunchKernelGGL((maxpy_kernel<T>), dim3(red_grid(pl->N)), dim3(RED_THREADS), 0, st, V, ldv, k, w, w, pl->N,
-                     cmode, pl->part, ks, emode, col, hstat, skip, skip2);
+static void norm_red(fde_plan pl, const T* a, const T* b, T* out, KState* ks, int emode, hipStream_t st,
+                     const int* skip = nullptr, const int* skip2 = nullptr) {
+  const int G = red_grid(pl->N, (long)RED_THREADS * 8);
+  hipLaunchKernelGGL((norm_kernel<T>), dim3(G), dim3(RED_THREADS), 0, st, a, b, out, pl->N, pl->part, ks, emode,
+                     skip, skip2);
+  finalize(pl, G, 1, ks, FK_NORM, emode, 0, nullptr, st, skip, skip2);
+}
+
+template <typename T, int KC, int EPI, int MODE>
+static void cgs_launch(fde_plan pl, const T* V, int k, T* w, KState* ks, int emode, int col, double* hstat,
+                       hipStream_t st, const int* skip, const int* skip2) {
+  const long N = pl->N;
+  const int G = red_grid(N, (long)RED_THREADS * EPI * 2);
+  const int cls = sizeof(T) == 8 ? (MODE == CG_DOT ? FDE_PROBE_MDOT64 : FDE_PROBE_MAXPY64)
+                                 : (MODE == CG_DOT ? FDE_PROBE_MDOT32 : FDE_PROBE_MAXPY32);
+  const double bytes = (double)(k + (MODE == CG_DOT ? 1 : 2)) * N * sizeof(T);
+  {
+    ProbeScope ps(pl, cls, st, bytes);
+    hipLaunchKernelGGL((cgs_kernel<T, KC, EPI, MODE>), dim3(G), dim3(RED_THREADS), 0, st, V, N, k, w, w, N, emode,
+                       col, pl->part, ks, hstat, skip, skip2);
+  }
+  if (MODE == CG_AXPY_NORM) finalize(pl, G, 1, ks, FK_NORM, emode, col, hstat, st, skip, skip2);
+  else finalize(pl, G, k, ks, FK_H, MODE == CG_AXPY_DOT ? EP_H2 : emode, col, hstat, st, skip, skip2);
+}
+
+template <typename T, int MODE>
+static void cgs_pass(fde_plan pl, const T* V, int k, T* w, KState* ks, int emode, int col, double* hstat,
+                     hipStream_t st, const int* skip, const int* skip2) {
+  if (k <= 8) cgs_launch<T, 8, 4, MODE>(pl, V, k, w, ks, emode, col, hstat, st, skip, skip2);
+  else if (k <= 16) cgs_launch<T, 16, 2, MODE>(pl, V, k, w, ks, emode, col, hstat, st, skip, skip2);
+  else cgs_launch<T, 32, 1, MODE>(pl, V, k, w, ks, emode, col, hstat, st, skip, skip2);
 }
 
 // CGS2 of w (= basis slot j+1) against basis vectors 0..j, then the Givens
-// column j.
+// column j: h1 = V^T w; w -= V h1 and h2 = V^T w in one pass; w -= V h2 and
+// ||w|| in one pass.
 template <typename T>
 static void cgs2_givens(fde_plan pl, const T* V, T* w, int j, KState* ks, double* hstat, hipStream_t st,
                         const int* skip, const int* skip2) {
-  const long N = pl->N;
-  mdot<T>(pl, V, N, j + 1, w, ks, EP_H1, st, skip, skip2);
-  maxpy<T>(pl, V, N, j + 1, w, EP_H1, ks, EP_NONE, j, nullptr, st, skip, skip2);
-  mdot<T>(pl, V, N, j + 1, w, ks, EP_H2, st, skip, skip2);
-  maxpy<T>(pl, V, N, j + 1, w, EP_H2, ks, EP_GIVENS, j, hstat, st, skip, skip2);
+  const int k = j + 1;
+  cgs_pass<T, CG_DOT>(pl, V, k, w, ks, EP_H1, j, nullptr, st, skip, skip2);
+  cgs_pass<T, CG_AXPY_DOT>(pl, V, k, w, ks, EP_H2, j, nullptr, st, skip, skip2);
+  cgs_pass<T, CG_AXPY_NORM>(pl, V, k, w, ks, EP_GIVENS, j, hstat, st, skip, skip2);
 }
 
 static fde_status read_header(fde_plan pl, KState* ks, hipStream_t st) {
@@ -913,7 +1013,7 @@ static void outer_step(fde_plan pl, int j, hipStream_t st) {
   double* w = pl->V + (long)(j + 1) * N;
   double* zj = pl->Z + (long)j * N;
   if (pl->p.precision == FDE_FP64) {
-    tau_matvec<double>(pl, vj, &ks->scale[j], zj, w, pl->t1, pl->t2, pl->t3, st, skip);
+    tau_matvec<double>(pl, vj, &ks->scale[j], zj, w, st, skip, nullptr);
   } else {
     KState* ki = pl->ksi;
     const int* s2 = &ki->done;
@@ -924,23 +1024,22 @@ static void outer_step(fde_plan pl, int j, hipStream_t st) {
       float* Vf = pl->Vf;
       hipLaunchKernelGGL((scale_cast_kernel<double, float>), dim3(ew_grid(N)), dim3(256), 0, st, vj, Vf, N,
                          &ks->scale[j], skip, nullptr);
-      hipLaunchKernelGGL((norm_kernel<float>), dim3(red_grid(N)), dim3(RED_THREADS), 0, st, Vf, nullptr, nullptr, N,
-                         pl->part, ki, EP_INNER0, skip, nullptr);
+      norm_red<float>(pl, Vf, nullptr, nullptr, ki, EP_INNER0, st, skip, nullptr);
       for (int i = 0; i < pl->kin; ++i) {
         float* vi = Vf + (long)i * N;
         float* wi = Vf + (long)(i + 1) * N;
         // inner kernels skip when the outer cycle is over or the inner one broke down
-        tau_matvec<float>(pl, vi, &ki->scale[i], nullptr, wi, pl->t1f, pl->t2f, pl->t3f, st, s2);
+        tau_matvec<float>(pl, vi, &ki->scale[i], pl->zf, wi, st, s2, skip);
         cgs2_givens<float>(pl, Vf, wi, i, ki, nullptr, st, s2, skip);
       }
-      hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(64), 0, st, ki, skip);
+      hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(256), 0, st, ki, skip);
       hipLaunchKernelGGL((update_kernel<float, float>), dim3(ew_grid(N)), dim3(RED_THREADS), 0, st, Vf, N,
                          (const float*)nullptr, pl->uf, N, ki, ki->scale, skip);
     }
-    tau_only<float>(pl, pl->uf, nullptr, pl->zf, pl->t1f, pl->t2f, st, skip);
+    tau_only<float>(pl, pl->uf, nullptr, pl->zf, st, skip);
     hipLaunchKernelGGL((scale_cast_kernel<float, double>), dim3(ew_grid(N)), dim3(256), 0, st, pl->zf, zj, N,
                        nullptr, skip, nullptr);
-    matvec_only<double>(pl, zj, w, pl->t3, pl->nu, 1.0, st, skip);
+    matvec_only<double>(pl, zj, w, pl->nu, 1.0, st, skip);
   }
   cgs2_givens<double>(pl, pl->V, w, j, ks, pl->hstat_dev, st, skip, nullptr);
 }
@@ -948,9 +1047,8 @@ static void outer_step(fde_plan pl, int j, hipStream_t st) {
 // r = b - M x into basis slot 0 and its norm (cycle start / true residual).
 static void residual(fde_plan pl, const double* b, const double* x, hipStream_t st) {
   double* tmp = pl->V + pl->N;   // slot 1 is free between cycles
-  matvec_only<double>(pl, x, tmp, pl->t3, pl->nu, 1.0, st, nullptr);
-  hipLaunchKernelGGL((norm_kernel<double>), dim3(red_grid(pl->N)), dim3(RED_THREADS), 0, st, b, tmp, pl->V, pl->N,
-                     pl->part, pl->ks, EP_RESID, nullptr, nullptr);
+  matvec_only<double>(pl, x, tmp, pl->nu, 1.0, st, nullptr);
+  norm_red<double>(pl, b, tmp, pl->V, pl->ks, EP_RESID, st);
 }
 
 static fde_status solve_gmres(fde_plan pl, const double* b, double* x, fde_info* info, hipStream_t st) {
@@ -958,14 +1056,12 @@ static fde_status solve_gmres(fde_plan pl, const double* b, double* x, fde_info*
   KState* ks = pl->ks;
   hipLaunchKernelGGL(ks_init_kernel, dim3(1), dim3(1), 0, st, ks, pl->p.maxit, pl->m, pl->p.tol);
   hipLaunchKernelGGL(ks_init_kernel, dim3(1), dim3(1), 0, st, pl->ksi, 1 << 30, std::max(1, pl->kin), 0.0);
-  hipLaunchKernelGGL((norm_kernel<double>), dim3(red_grid(N)), dim3(RED_THREADS), 0, st, b, (const double*)nullptr,
-                     (double*)nullptr, N, pl->part, ks, EP_BNORM, nullptr, nullptr);
+  norm_red<double>(pl, b, nullptr, nullptr, ks, EP_BNORM, st);
   hipLaunchKernelGGL(ks_settol_kernel, dim3(1), dim3(1), 0, st, ks);
   residual(pl, b, x, st);
   HIPCHK(hipGetLastError());
   TRY(read_header(pl, ks, st));
-  if (pl->hks->nonfinite && !std::isfinite(pl->hks->bnorm))
-    return fail(FDE_ENONFINITE, "the right-hand side has a non-finite value");
+  if (!std::isfinite(pl->hks->bnorm)) return fail(FDE_ENONFINITE, "the right-hand side has a non-finite value");
   if (pl->hks->bnorm == 0.0) {
     hipLaunchKernelGGL(axpby_kernel, dim3(ew_grid(N)), dim3(256), 0, st, 0.0, b, 0.0, (const double*)nullptr, x, N);
     HIPCHK(hipStreamSynchronize(st));
@@ -983,7 +1079,7 @@ static fde_status solve_gmres(fde_plan pl, const double* b, double* x, fde_info*
       outer_step(pl, j, st);
       HIPCHK(hipEventRecord(pl->ev[j & 3], st));
     }
-    hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(64), 0, st, ks, (const int*)nullptr);
+    hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(256), 0, st, ks, (const int*)nullptr);
     hipLaunchKernelGGL((update_kernel<double, double>), dim3(ew_grid(N)), dim3(RED_THREADS), 0, st, pl->Z, N, x, x,
                        N, ks, (const double*)nullptr, (const int*)nullptr);
     residual(pl, b, x, st);
@@ -991,7 +1087,7 @@ static fde_status solve_gmres(fde_plan pl, const double* b, double* x, fde_info*
     TRY(read_header(pl, ks, st));
     if (!pl->hks->conv) ++restarts;
   }
-  const KState& h = *pl->hks;
+  const KState h = *pl->hks;
   if (info) {
     info->iters = h.iters;
     info->restarts = restarts;
@@ -1002,12 +1098,18 @@ static fde_status solve_gmres(fde_plan pl, const double* b, double* x, fde_info*
     if (pl->p.precision == FDE_MIXED) {
       TRY(read_header(pl, pl->ksi, st));
       info->inner_iters = pl->hks->iters;
-      TRY(read_header(pl, ks, st));
     }
   }
   if (h.nonfinite) return fail(FDE_ENONFINITE, "a residual became non-finite");
   if (!h.conv) return fail(FDE_ENOTCONV, "tolerance not reached in %d iterations", h.iters);
   return FDE_OK;
+}
+
+template <typename T>
+static void dot_red(fde_plan pl, const T* a, const T* b, KState* ks, int emode, hipStream_t st, const int* skip) {
+  const int G = red_grid(pl->N, (long)RED_THREADS * 8);
+  hipLaunchKernelGGL((dot_kernel<T>), dim3(G), dim3(RED_THREADS), 0, st, a, b, pl->N, pl->part, ks, emode, skip);
+  finalize(pl, G, 1, ks, FK_DOT, emode, 0, nullptr, st, skip, nullptr);
 }
 
 static fde_status solve_pcg(fde_plan pl, const double* b, double* x, fde_info* info, hipStream_t st) {
@@ -1019,12 +1121,10 @@ static fde_status solve_pcg(fde_plan pl, const double* b, double* x, fde_info* i
   double* q = pl->V + 2 * N;
   double* z = pl->Z;
   hipLaunchKernelGGL(ks_init_kernel, dim3(1), dim3(1), 0, st, ks, pl->p.maxit, 1, pl->p.tol);
-  hipLaunchKernelGGL((norm_kernel<double>), dim3(red_grid(N)), dim3(RED_THREADS), 0, st, b, (const double*)nullptr,
-                     (double*)nullptr, N, pl->part, ks, EP_BNORM, nullptr, nullptr);
+  norm_red<double>(pl, b, nullptr, nullptr, ks, EP_BNORM, st);
   hipLaunchKernelGGL(ks_settol_kernel, dim3(1), dim3(1), 0, st, ks);
-  matvec_only<double>(pl, x, q, pl->t3, pl->nu, 1.0, st, nullptr);
-  hipLaunchKernelGGL((norm_kernel<double>), dim3(red_grid(N)), dim3(RED_THREADS), 0, st, b, q, r, N, pl->part, ks,
-                     EP_RESID, nullptr, nullptr);
+  matvec_only<double>(pl, x, q, pl->nu, 1.0, st, nullptr);
+  norm_red<double>(pl, b, q, r, ks, EP_RESID, st);
   HIPCHK(hipGetLastError());
   TRY(read_header(pl, ks, st));
   if (!std::isfinite(pl->hks->bnorm)) return fail(FDE_ENONFINITE, "the right-hand side has a non-finite value");
@@ -1034,12 +1134,12 @@ static fde_status solve_pcg(fde_plan pl, const double* b, double* x, fde_info* i
     if (info) *info = fde_info{0, 0, 0, 1, 0.0, 0.0, 0.0};
     return FDE_OK;
   }
+  const int G = red_grid(N, (long)RED_THREADS * 8);
   int restarts = 0;
   while (!pl->hks->conv && !pl->hks->nonfinite && pl->hks->iters < pl->p.maxit) {
     // (re)start: z = P^{-1} r, rz = r.z, p = z
-    tau_only<double>(pl, r, nullptr, z, pl->t1, pl->t2, st, skip);
-    hipLaunchKernelGGL((dot_kernel<double>), dim3(red_grid(N)), dim3(RED_THREADS), 0, st, r, z, N, pl->part, ks,
-                       EP_CG_RZ, skip);
+    tau_only<double>(pl, r, nullptr, z, st, skip);
+    dot_red<double>(pl, r, z, ks, EP_CG_RZ, st, skip);
     hipLaunchKernelGGL((scale_cast_kernel<double, double>), dim3(ew_grid(N)), dim3(256), 0, st, z, p, N,
                        (const double*)nullptr, skip, (const int*)nullptr);
     pl->hstat[0] = 0.0;
@@ -1048,26 +1148,24 @@ static fde_status solve_pcg(fde_plan pl, const double* b, double* x, fde_info* i
         HIPCHK(hipEventSynchronize(pl->ev[(it - 2) & 3]));
         if (*(volatile double*)&pl->hstat[0] != 0.0) break;
       }
-      matvec_only<double>(pl, p, q, pl->t3, pl->nu, 1.0, st, skip);
-      hipLaunchKernelGGL((dot_kernel<double>), dim3(red_grid(N)), dim3(RED_THREADS), 0, st, p, q, N, pl->part, ks,
-                         EP_CG_PQ, skip);
-      hipLaunchKernelGGL(cg_update_kernel, dim3(red_grid(N)), dim3(RED_THREADS), 0, st, x, r, p, q, N, pl->part,
-                         ks, pl->hstat_dev, skip);
-      tau_only<double>(pl, r, nullptr, z, pl->t1, pl->t2, st, skip);
-      hipLaunchKernelGGL((dot_kernel<double>), dim3(red_grid(N)), dim3(RED_THREADS), 0, st, r, z, N, pl->part, ks,
-                         EP_CG_RZ, skip);
+      matvec_only<double>(pl, p, q, pl->nu, 1.0, st, skip);
+      dot_red<double>(pl, p, q, ks, EP_CG_PQ, st, skip);
+      hipLaunchKernelGGL(cg_update_kernel, dim3(G), dim3(RED_THREADS), 0, st, x, r, p, q, N, pl->part, ks,
+                         pl->hstat_dev, skip);
+      finalize(pl, G, 1, ks, FK_NORM, EP_CG_R, 0, pl->hstat_dev, st, skip, nullptr);
+      tau_only<double>(pl, r, nullptr, z, st, skip);
+      dot_red<double>(pl, r, z, ks, EP_CG_RZ, st, skip);
       hipLaunchKernelGGL(cg_direction_kernel, dim3(ew_grid(N)), dim3(256), 0, st, p, z, N, ks, skip);
       HIPCHK(hipEventRecord(pl->ev[it & 3], st));
     }
     // true residual
-    matvec_only<double>(pl, x, q, pl->t3, pl->nu, 1.0, st, nullptr);
-    hipLaunchKernelGGL((norm_kernel<double>), dim3(red_grid(N)), dim3(RED_THREADS), 0, st, b, q, r, N, pl->part, ks,
-                       EP_RESID, nullptr, nullptr);
+    matvec_only<double>(pl, x, q, pl->nu, 1.0, st, nullptr);
+    norm_red<double>(pl, b, q, r, ks, EP_RESID, st);
     HIPCHK(hipGetLastError());
     TRY(read_header(pl, ks, st));
     if (!pl->hks->conv) ++restarts;
   }
-  const KState& h = *pl->hks;
+  const KState h = *pl->hks;
   if (info) {
     info->iters = h.iters;
     info->inner_iters = 0;

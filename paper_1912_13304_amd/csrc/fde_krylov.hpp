@@ -1,11 +1,13 @@
 // Krylov building blocks on the device: the solver state lives in device
 // memory, so one Arnoldi step is a fixed sequence of launches with no host
 // round trip.  Reductions are deterministic: every workgroup writes its
-// partial sums, and the last workgroup to finish (found with a device-scope
-// counter) adds the partials in a fixed order and runs a scalar epilogue
-// (Gram-Schmidt coefficients, the Givens rotation of a new Hessenberg column,
-// residual checks, PCG scalars).  Results therefore do not depend on how many
-// other solves share the GPU.
+// partial sums; a one-workgroup finalize kernel (or the reduction kernel
+// itself when its grid is a single workgroup) adds the partials in a fixed
+// order and runs a scalar epilogue (Gram-Schmidt coefficients, the Givens
+// rotation of a new Hessenberg column, residual checks, PCG scalars).  The
+// kernel boundary publishes the partials across the XCDs' L2 caches, which a
+// grid-wide fence would do only by writing back whole caches from every
+// workgroup.  Results do not depend on how many other solves share the GPU.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,7 +20,7 @@ namespace fde {
 constexpr int KMAX = 64;          // largest GMRES cycle
 constexpr int RED_THREADS = 256;  // reduction workgroup size
 constexpr int RED_EPT = 8;        // elements per thread in a reduction pass
-constexpr int RED_MAXG = 512;     // largest reduction grid
+constexpr int RED_MAXG = 1024;    // largest reduction grid
 
 // Scalar state of one (F)GMRES or PCG solve.  The header fields come first
 // so that the host can copy them back cheaply.
@@ -34,11 +36,11 @@ struct KState {
   int breakdown;
   double bnorm, tolabs, beta, est, hn;
   double rz, pq, alpha, betacg;
-  unsigned counter; // last-workgroup counter (reset by the last workgroup)
-  int pad_;
+  int pad0_, pad1_;
   // ---- body ----
   double scale[KMAX + 1];   // basis vector i = scale[i] * stored vector i
   double h1[KMAX + 1], h2[KMAX + 1];
+  double c1[KMAX + 1], c2[KMAX + 1];   // update coefficients scale[i] * h1[i], scale[i] * h2[i]
   double cs[KMAX], sn[KMAX], g[KMAX + 1], y[KMAX];
   double R[KMAX * (KMAX + 1)];   // column j at R[j*(KMAX+1) + i]
 };
@@ -55,45 +57,7 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sum NV values over the workgroup; lane 0 of wave 0 returns the totals in
-// out[] (other threads: unspecified).  Uses red[NV * 4] doubles of LDS.
-template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nw = blockDim.x >> 6;
-#pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    const double s = wave_sum(v[q]);
-    if (lane == 0) red[q * 16 + wave] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      double s = 0.0;
-      for (int w = 0; w < nw; ++w) s += red[q * 16 + w];
-      v[q] = s;
-    }
-  }
-  __syncthreads();
-}
-
-// Publish this workgroup's partials and find out whether it is the last
-// workgroup of the grid.  `nparts` values part[q*G + b] were written by thread 0.
-__device__ __forceinline__ bool last_block(unsigned* counter) {
-  __shared__ int s_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(counter, 1u);
-    s_last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (s_last) __threadfence();
-  return s_last;
-}
-
-// In the last workgroup: tot[q] = sum_b part[q*G + b] in a fixed order, for
+// One workgroup: tot[q] = sum_b part[q*G + b] in a fixed order, for
 // q < nq.  Each wavefront owns values q = wave, wave+nw, ...; lanes add a
 // strided subset and a fixed shuffle tree finishes.  Result in tot (LDS).
 __device__ __forceinline__ void reduce_parts(const double* part, int G, int nq, double* tot) {
@@ -113,40 +77,46 @@ __device__ __forceinline__ void reduce_parts(const double* part, int G, int nq, 
 // ---------------------------------------------------------------------------
 
 // New Hessenberg column j from h = h1 + h2 (i <= j) and hn = ||w||; applies
-// the earlier rotations, forms rotation j, updates g and the residual estimate.
-__device__ inline void givens_column(KState* ks, int j, double hn) {
-  double h[KMAX + 1];
-  for (int i = 0; i <= j; ++i) h[i] = ks->h1[i] + ks->h2[i];
-  h[j + 1] = hn;
+// the earlier rotations, forms rotation j, updates g and the residual
+// estimate.  Run by the 64 lanes of one wavefront: lane i holds h_i, and the
+// rotation of rows (i, i+1) reads both entries with readlane.
+__device__ inline void givens_column_wave(KState* ks, int j, double hn) {
+  const int lane = threadIdx.x & 63;
+  double h = 0.0;
+  if (lane <= j) h = ks->h1[lane] + ks->h2[lane];
+  else if (lane == j + 1) h = hn;
   for (int i = 0; i < j; ++i) {
-    const double a = h[i], b = h[i + 1];
-    h[i] = ks->cs[i] * a + ks->sn[i] * b;
-    h[i + 1] = -ks->sn[i] * a + ks->cs[i] * b;
+    const double c = ks->cs[i], s = ks->sn[i];
+    const double a = __shfl(h, i, 64), b = __shfl(h, i + 1, 64);
+    if (lane == i) h = c * a + s * b;
+    else if (lane == i + 1) h = -s * a + c * b;
   }
-  const double a = h[j], b = h[j + 1];
-  const double rho = hypot(a, b);
+  const double a = __shfl(h, j, 64);
+  const double rho = hypot(a, hn);
   double c = 1.0, s = 0.0;
   if (rho != 0.0) {
     c = a / rho;
-    s = b / rho;
+    s = hn / rho;
   }
-  ks->cs[j] = c;
-  ks->sn[j] = s;
-  h[j] = rho;
-  for (int i = 0; i <= j; ++i) ks->R[j * (KMAX + 1) + i] = h[i];
-  const double gj = ks->g[j];
-  ks->g[j + 1] = -s * gj;
-  ks->g[j] = c * gj;
-  const double est = fabs(ks->g[j + 1]);
-  ks->est = est;
-  ks->hn = hn;
-  ks->kdone = j + 1;
-  ks->iters += 1;
-  const bool bad = !isfinite(est) || !isfinite(hn);
-  if (bad) ks->nonfinite = 1;
-  if (hn == 0.0) ks->breakdown = 1;
-  ks->scale[j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
-  ks->done = (est <= ks->tolabs) || hn == 0.0 || bad || (ks->iters >= ks->maxit) || (j + 1 >= ks->m);
+  if (lane == j) h = rho;
+  if (lane <= j) ks->R[j * (KMAX + 1) + lane] = h;
+  if (lane == 0) {
+    ks->cs[j] = c;
+    ks->sn[j] = s;
+    const double gj = ks->g[j];
+    ks->g[j + 1] = -s * gj;
+    ks->g[j] = c * gj;
+    const double est = fabs(ks->g[j + 1]);
+    ks->est = est;
+    ks->hn = hn;
+    ks->kdone = j + 1;
+    ks->iters += 1;
+    const bool bad = !isfinite(est) || !isfinite(hn);
+    if (bad) ks->nonfinite = 1;
+    if (hn == 0.0) ks->breakdown = 1;
+    ks->scale[j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
+    ks->done = (est <= ks->tolabs) || hn == 0.0 || bad || (ks->iters >= ks->maxit) || (j + 1 >= ks->m);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -166,15 +136,20 @@ enum : int {
   EP_NONE = 9,
 };
 
+// Scalar epilogue of a norm reduction; called by the 64 lanes of wave 0 of
+// the last workgroup (only the Givens step uses more than lane 0).
 __device__ inline void epilogue_norm(KState* ks, int mode, int col, double ss, double* hstat) {
   const double nrm = sqrt(ss);
   if (mode == EP_GIVENS) {
-    givens_column(ks, col, nrm);
-    if (hstat) {
+    givens_column_wave(ks, col, nrm);
+    if ((threadIdx.x & 63) == 0 && hstat) {
       hstat[0] = (double)ks->done;
       hstat[1] = (double)ks->iters;
     }
-  } else if (mode == EP_RESID) {
+    return;
+  }
+  if ((threadIdx.x & 63) != 0) return;
+  if (mode == EP_RESID) {
     ks->beta = nrm;
     if (!isfinite(nrm)) ks->nonfinite = 1;
     ks->conv = nrm <= ks->tolabs;
@@ -207,88 +182,195 @@ __device__ inline void epilogue_norm(KState* ks, int mode, int col, double ss, d
   }
 }
 
-// h_q = scale[q] * <V_q, w>, q < k  (k read from *kp when kp != null).
-template <typename T>
-__global__ void __launch_bounds__(RED_THREADS)
-mdot_kernel(const T* __restrict__ V, long ldv, int k, const T* __restrict__ w, long N,
-            double* part, KState* ks, int mode, const int* skip, const int* skip2) {
-  if (skipped(skip, skip2)) return;
-  __shared__ double red[8 * 16];
-  __shared__ double tot[KMAX + 1];
-  const int G = gridDim.x;
-  const long stride = (long)G * RED_THREADS;
-  const long e0 = (long)blockIdx.x * RED_THREADS + threadIdx.x;
-  for (int q0 = 0; q0 < k; q0 += 8) {
-    double acc[8];
+// ---------------------------------------------------------------------------
+// Multi-value reductions for the Gram-Schmidt kernels.
+// ---------------------------------------------------------------------------
+
+// Sum KC values (KC a power of two <= 64) over the 64 lanes of a wavefront
+// with a butterfly that halves the number of values per lane at each step:
+// at step s the partner is lane ^ (32 >> s) and each lane keeps one half.
+// Afterwards lane L holds the wave total of value L >> (6 - log2 KC).
+template <int KC>
+__device__ __forceinline__ double wave_multi_sum(double (&a)[KC]) {
+  const int lane = threadIdx.x & 63;
+  constexpr int LG = KC <= 1 ? 0 : KC <= 2 ? 1 : KC <= 4 ? 2 : KC <= 8 ? 3 : KC <= 16 ? 4 : KC <= 32 ? 5 : 6;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-    for (long e = e0; e < N; e += stride) {
-      const double wv = (double)w[e];
+  for (int s = 0; s < LG; ++s) {
+    const int m = 32 >> s;
+    const int half = KC >> (s + 1);
+    const bool upper = (lane & m) != 0;
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (q0 + q < k) acc[q] += (double)V[(long)(q0 + q) * ldv + e] * wv;
-    }
-    block_sum<8>(acc, red);
-    if (threadIdx.x == 0) {
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (q0 + q < k) part[(size_t)(q0 + q) * G + blockIdx.x] = acc[q];
+    for (int i = 0; i < half; ++i) {
+      const double lo = a[i], hi = a[i + half];
+      const double send = upper ? lo : hi;
+      const double keep = upper ? hi : lo;
+      a[i] = keep + __shfl_xor(send, m, 64);
     }
   }
-  if (!last_block(&ks->counter)) return;
-  reduce_parts(part, G, k, tot);
-  if (threadIdx.x == 0) {
-    double* dst = mode == EP_H1 ? ks->h1 : ks->h2;
-    for (int q = 0; q < k; ++q) dst[q] = ks->scale[q] * tot[q];
-    ks->counter = 0;
+#pragma unroll
+  for (int s = 0; s < 6 - LG; ++s) {
+    const int m = (32 >> LG) >> s;
+    a[0] += __shfl_xor(a[0], m, 64);
+  }
+  return a[0];
+}
+
+// Workgroup totals of KC values into tot[0..KC) (LDS, fixed order over waves).
+template <int KC>
+__device__ __forceinline__ void block_multi_sum(double (&a)[KC], double* red, double* tot) {
+  constexpr int LG = KC <= 1 ? 0 : KC <= 2 ? 1 : KC <= 4 ? 2 : KC <= 8 ? 3 : KC <= 16 ? 4 : KC <= 32 ? 5 : 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const double v = wave_multi_sum<KC>(a);
+  if ((lane & ((1 << (6 - LG)) - 1)) == 0) red[wave * KC + (lane >> (6 - LG))] = v;
+  __syncthreads();
+  if ((int)threadIdx.x < KC) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[w * KC + threadIdx.x];
+    tot[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+
+// What a reduction's scalar epilogue does with its totals.
+enum : int { FK_H = 0,      // tot[0..nq) -> h (emode EP_H1/EP_H2) and the update coefficients
+             FK_NORM = 1,   // tot[0] = sum of squares -> epilogue_norm(emode)
+             FK_DOT = 2 };  // tot[0] = dot product -> PCG scalars (emode EP_CG_PQ / EP_CG_RZ)
+
+// Scalar epilogue; called by every thread of one workgroup once tot[] is in LDS.
+__device__ inline void finish(const double* tot, int nq, KState* ks, int fkind, int emode, int col,
+                              double* hstat) {
+  if (fkind == FK_H) {
+    const bool second = emode == EP_H2;
+    double* dst = second ? ks->h2 : ks->h1;
+    double* cdst = second ? ks->c2 : ks->c1;
+    for (int q = threadIdx.x; q < nq; q += blockDim.x) {
+      const double hq = ks->scale[q] * tot[q];
+      dst[q] = hq;
+      cdst[q] = ks->scale[q] * hq;
+    }
+  } else if (fkind == FK_NORM) {
+    if (threadIdx.x < 64) epilogue_norm(ks, emode, col, tot[0], hstat);
+  } else if (threadIdx.x == 0) {
+    const double s = tot[0];
+    if (emode == EP_CG_PQ) {
+      ks->pq = s;
+      ks->alpha = ks->rz / s;
+    } else if (emode == EP_CG_RZ) {
+      ks->betacg = (ks->rz != 0.0 && ks->iters > 0) ? s / ks->rz : 0.0;
+      ks->rz = s;
+    }
   }
 }
 
-// out = w - sum_q scale[q] * c[q] * V_q for q < k, where c = ks->h1 or ks->h2
-// (mode EP_H1/EP_H2 select the coefficients); then optionally ||out||^2 with
-// a norm epilogue (emode).  out may alias w.
-template <typename T>
+// End of a reduction kernel: publish the workgroup totals tot[0..nq) as
+// partials, or finish in place when the grid is one workgroup.
+__device__ inline void publish_or_finish(double* tot, int nq, double* part, KState* ks, int fkind, int emode,
+                                         int col, double* hstat) {
+  if (gridDim.x == 1) {
+    finish(tot, nq, ks, fkind, emode, col, hstat);
+    return;
+  }
+  for (int q = threadIdx.x; q < nq; q += blockDim.x) part[(size_t)q * gridDim.x + blockIdx.x] = tot[q];
+}
+
+// One-workgroup finalize: tot[q] = sum_b part[q*G + b] for q < nq <= KC, in a
+// fixed order, then the scalar epilogue.  Thread t adds partials b = t,
+// t + 256, ... of every value (coalesced, all loads independent), and the
+// workgroup butterfly reduction finishes.
+template <int KC>
 __global__ void __launch_bounds__(RED_THREADS)
-maxpy_kernel(const T* __restrict__ V, long ldv, int k, const T* w, T* out, long N, int cmode,
-             double* part, KState* ks, int emode, int col, double* hstat, const int* skip,
-             const int* skip2) {
+finalize_kernel(const double* part, int G, int nq, KState* ks, int fkind, int emode, int col, double* hstat,
+                const int* skip, const int* skip2) {
   if (skipped(skip, skip2)) return;
-  __shared__ double red[1 * 16];
-  __shared__ double coef[KMAX + 1];
-  const double* c = cmode == EP_H1 ? ks->h1 : ks->h2;
-  for (int q = threadIdx.x; q < k; q += blockDim.x) coef[q] = ks->scale[q] * c[q];
-  __syncthreads();
-  const int G = gridDim.x;
-  const long stride = (long)G * RED_THREADS;
-  double ss[1] = {0.0};
-  for (long e = (long)blockIdx.x * RED_THREADS + threadIdx.x; e < N; e += stride) {
-    double acc = (double)w[e];
-    for (int q = 0; q < k; ++q) acc -= coef[q] * (double)V[(long)q * ldv + e];
-    const T r = (T)acc;
-    out[e] = r;
-    ss[0] += (double)r * (double)r;
+  __shared__ double red[16 * KC];
+  __shared__ double tot[KC];
+  double acc[KC];
+#pragma unroll
+  for (int q = 0; q < KC; ++q) acc[q] = 0.0;
+  for (int b = threadIdx.x; b < G; b += RED_THREADS) {
+#pragma unroll
+    for (int q = 0; q < KC; ++q)
+      if (q < nq) acc[q] += part[(size_t)q * G + b];
   }
-  if (emode == EP_NONE) return;
-  block_sum<1>(ss, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = ss[0];
-  if (!last_block(&ks->counter)) return;
-  __shared__ double tot[1];
-  reduce_parts(part, G, 1, tot);
-  if (threadIdx.x == 0) {
-    epilogue_norm(ks, emode, col, tot[0], hstat);
-    ks->counter = 0;
+  block_multi_sum<KC>(acc, red, tot);
+  finish(tot, nq, ks, fkind, emode, col, hstat);
+}
+
+// Classical Gram-Schmidt passes against the k <= KC basis vectors of V
+// (stored vectors; basis vector q = scale[q] * V_q).  Every thread loads the
+// k basis values of EPI elements at once, so a pass reads each operand once
+// with k*EPI loads in flight per thread.
+//   CG_DOT       h_q = scale[q] <V_q, w>                     -> ks->h1 (emode EP_H1) or h2
+//   CG_AXPY_DOT  out = w - sum_q scale[q] h1[q] V_q,  h2_q = scale[q] <V_q, out>
+//   CG_AXPY_NORM out = w - sum_q scale[q] h2[q] V_q,  ||out|| -> Givens column `col`
+enum : int { CG_DOT = 0, CG_AXPY_DOT = 1, CG_AXPY_NORM = 2 };
+
+template <typename T, int KC, int EPI, int MODE>
+__global__ void __launch_bounds__(RED_THREADS)
+cgs_kernel(const T* __restrict__ V, long ldv, int k, const T* w, T* out, long N, int emode, int col,
+           double* part, KState* ks, double* hstat, const int* skip, const int* skip2) {
+  if (skipped(skip, skip2)) return;
+  constexpr int NA = MODE == CG_AXPY_NORM ? 1 : KC;
+  __shared__ double red[16 * NA];
+  __shared__ double tot[NA > KMAX + 1 ? NA : KMAX + 1];
+  double coef[KC];   // uniform: kept in scalar registers
+  if (MODE != CG_DOT) {
+    const double* c = MODE == CG_AXPY_DOT ? ks->c1 : ks->c2;
+#pragma unroll
+    for (int q = 0; q < KC; ++q) coef[q] = q < k ? c[q] : 0.0;
   }
+  double acc[NA];
+#pragma unroll
+  for (int q = 0; q < NA; ++q) acc[q] = 0.0;
+  const long step = (long)gridDim.x * RED_THREADS * EPI;
+  for (long e0 = (long)blockIdx.x * RED_THREADS * EPI + threadIdx.x; e0 < N; e0 += step) {
+    T vq[EPI][KC];
+    double x[EPI];
+    bool ok[EPI];
+#pragma unroll
+    for (int i = 0; i < EPI; ++i) {
+      const long e = e0 + (long)i * RED_THREADS;
+      ok[i] = e < N;
+      x[i] = ok[i] ? (double)w[e] : 0.0;
+#pragma unroll
+      for (int q = 0; q < KC; ++q) vq[i][q] = (ok[i] && q < k) ? V[(long)q * ldv + e] : T(0);
+    }
+    if (MODE != CG_DOT) {
+#pragma unroll
+      for (int i = 0; i < EPI; ++i) {
+#pragma unroll
+        for (int q = 0; q < KC; ++q) x[i] -= coef[q] * (double)vq[i][q];
+        const T r = (T)x[i];
+        if (ok[i]) out[e0 + (long)i * RED_THREADS] = r;
+        x[i] = (double)r;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < EPI; ++i) {
+      if (MODE == CG_AXPY_NORM) {
+        acc[0] += x[i] * x[i];
+      } else {
+#pragma unroll
+        for (int q = 0; q < KC; ++q) acc[q] += (double)vq[i][q] * x[i];
+      }
+    }
+  }
+  block_multi_sum<NA>(acc, red, tot);
+  if (MODE == CG_AXPY_NORM) publish_or_finish(tot, 1, part, ks, FK_NORM, emode, col, hstat);
+  else publish_or_finish(tot, k, part, ks, FK_H, MODE == CG_AXPY_DOT ? EP_H2 : emode, col, hstat);
 }
 
 // ||a - b||^2 (b may be null: ||a||^2); optionally writes out = a - b.
 template <typename T>
 __global__ void __launch_bounds__(RED_THREADS)
-norm_kernel(const T* a, const T* b, T* out, long N, double* part, KState* ks, int emode,
-            const int* skip, const int* skip2) {
+norm_kernel(const T* a, const T* b, T* out, long N, double* part, KState* ks, int emode, const int* skip,
+            const int* skip2) {
   if (skipped(skip, skip2)) return;
   __shared__ double red[16];
-  const int G = gridDim.x;
-  const long stride = (long)G * RED_THREADS;
+  __shared__ double tot[1];
+  const long stride = (long)gridDim.x * RED_THREADS;
   double ss[1] = {0.0};
   for (long e = (long)blockIdx.x * RED_THREADS + threadIdx.x; e < N; e += stride) {
     double v = (double)a[e];
@@ -297,27 +379,105 @@ norm_kernel(const T* a, const T* b, T* out, long N, double* part, KState* ks, in
     if (out) out[e] = r;
     ss[0] += (double)r * (double)r;
   }
-  block_sum<1>(ss, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = ss[0];
-  if (!last_block(&ks->counter)) return;
+  block_multi_sum<1>(ss, red, tot);
+  publish_or_finish(tot, 1, part, ks, FK_NORM, emode, 0, nullptr);
+}
+
+// Dot product a.b -> PCG scalar epilogue.
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS)
+dot_kernel(const T* a, const T* b, long N, double* part, KState* ks, int emode, const int* skip) {
+  if (skip && *skip) return;
+  __shared__ double red[16];
   __shared__ double tot[1];
-  reduce_parts(part, G, 1, tot);
+  const long stride = (long)gridDim.x * RED_THREADS;
+  double ss[1] = {0.0};
+  for (long e = (long)blockIdx.x * RED_THREADS + threadIdx.x; e < N; e += stride)
+    ss[0] += (double)a[e] * (double)b[e];
+  block_multi_sum<1>(ss, red, tot);
+  publish_or_finish(tot, 1, part, ks, FK_DOT, emode, 0, nullptr);
+}
+
+// PCG: x += alpha p; r -= alpha q; ||r||^2 -> recursive residual check.
+__global__ void __launch_bounds__(RED_THREADS)
+cg_update_kernel(double* x, double* r, const double* p, const double* q, long N, double* part, KState* ks,
+                 double* hstat, const int* skip) {
+  if (skip && *skip) return;
+  __shared__ double red[16];
+  __shared__ double tot[1];
+  const double al = ks->alpha;
+  const long stride = (long)gridDim.x * RED_THREADS;
+  double ss[1] = {0.0};
+  for (long e = (long)blockIdx.x * RED_THREADS + threadIdx.x; e < N; e += stride) {
+    x[e] += al * p[e];
+    const double rv = r[e] - al * q[e];
+    r[e] = rv;
+    ss[0] += rv * rv;
+  }
+  block_multi_sum<1>(ss, red, tot);
+  publish_or_finish(tot, 1, part, ks, FK_NORM, EP_CG_R, 0, hstat);
+}
+
+// Setup statistics: min, max and a non-finite flag of one array, grid-wide.
+__global__ void __launch_bounds__(RED_THREADS) stats_part_kernel(const double* a, long N, double* part) {
+  double mn = INFINITY, mx = -INFINITY, bad = 0.0;
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
+    const double v = a[e];
+    if (!isfinite(v)) bad = 1.0;
+    mn = fmin(mn, v);
+    mx = fmax(mx, v);
+  }
+  __shared__ double s[3][RED_THREADS];
+  s[0][threadIdx.x] = mn;
+  s[1][threadIdx.x] = mx;
+  s[2][threadIdx.x] = bad;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      s[0][threadIdx.x] = fmin(s[0][threadIdx.x], s[0][threadIdx.x + h]);
+      s[1][threadIdx.x] = fmax(s[1][threadIdx.x], s[1][threadIdx.x + h]);
+      s[2][threadIdx.x] = fmax(s[2][threadIdx.x], s[2][threadIdx.x + h]);
+    }
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
-    epilogue_norm(ks, emode, 0, tot[0], nullptr);
-    ks->counter = 0;
+    part[3 * blockIdx.x] = s[0][0];
+    part[3 * blockIdx.x + 1] = s[1][0];
+    part[3 * blockIdx.x + 2] = s[2][0];
   }
 }
 
-// y = R^{-1} g for the kdone columns of the cycle (one thread).
-__global__ void backsolve_kernel(KState* ks, const int* skip) {
-  if (skip && *skip) return;
+__global__ void stats_final_kernel(const double* part, int G, double* out) {
   if (threadIdx.x != 0) return;
+  double mn = INFINITY, mx = -INFINITY, bad = 0.0;
+  for (int b = 0; b < G; ++b) {
+    mn = fmin(mn, part[3 * b]);
+    mx = fmax(mx, part[3 * b + 1]);
+    bad = fmax(bad, part[3 * b + 2]);
+  }
+  out[0] = mn;
+  out[1] = mx;
+  out[2] = bad;
+}
+
+// y = R^{-1} g for the kdone columns of the cycle.  R is staged in LDS;
+// one wavefront solves column by column: after y_i is known every lane l < i
+// removes R[l][i] y_i from its right-hand side entry.
+__global__ void __launch_bounds__(256) backsolve_kernel(KState* ks, const int* skip) {
+  if (skip && *skip) return;
+  __shared__ double Rs[KMAX * (KMAX + 1)];
   const int k = ks->kdone;
+  for (int t = threadIdx.x; t < k * (KMAX + 1); t += blockDim.x) Rs[t] = ks->R[t];
+  __syncthreads();
+  if (threadIdx.x >= 64) return;
+  const int lane = threadIdx.x;
+  double r = lane < k ? ks->g[lane] : 0.0;
   for (int i = k - 1; i >= 0; --i) {
-    double s = ks->g[i];
-    for (int j2 = i + 1; j2 < k; ++j2) s -= ks->R[j2 * (KMAX + 1) + i] * ks->y[j2];
-    const double d = ks->R[i * (KMAX + 1) + i];
-    ks->y[i] = d != 0.0 ? s / d : 0.0;
+    const double d = Rs[i * (KMAX + 1) + i];
+    const double yi = d != 0.0 ? __shfl(r, i, 64) / d : 0.0;
+    if (lane == i) ks->y[i] = yi;
+    if (lane < i) r -= Rs[i * (KMAX + 1) + lane] * yi;
   }
 }
 
@@ -336,62 +496,6 @@ update_kernel(const TZ* __restrict__ Z, long ldz, const TX* x0, TX* x, long N, c
     double acc = x0 ? (double)x0[e] : 0.0;
     for (int q = 0; q < k; ++q) acc += coef[q] * (double)Z[(long)q * ldz + e];
     x[e] = (TX)acc;
-  }
-}
-
-// Two dot products in one pass: sum a.b -> PCG scalar epilogue.
-template <typename T>
-__global__ void __launch_bounds__(RED_THREADS)
-dot_kernel(const T* a, const T* b, long N, double* part, KState* ks, int emode, const int* skip) {
-  if (skip && *skip) return;
-  __shared__ double red[16];
-  const int G = gridDim.x;
-  const long stride = (long)G * RED_THREADS;
-  double ss[1] = {0.0};
-  for (long e = (long)blockIdx.x * RED_THREADS + threadIdx.x; e < N; e += stride)
-    ss[0] += (double)a[e] * (double)b[e];
-  block_sum<1>(ss, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = ss[0];
-  if (!last_block(&ks->counter)) return;
-  __shared__ double tot[1];
-  reduce_parts(part, G, 1, tot);
-  if (threadIdx.x == 0) {
-    const double s = tot[0];
-    if (emode == EP_CG_PQ) {
-      ks->pq = s;
-      ks->alpha = ks->rz / s;
-    } else if (emode == EP_CG_RZ) {
-      ks->betacg = (ks->rz != 0.0 && ks->iters > 0) ? s / ks->rz : 0.0;
-      ks->rz = s;
-    }
-    ks->counter = 0;
-  }
-}
-
-// PCG: x += alpha p; r -= alpha q; ||r||^2 -> recursive residual check.
-__global__ void __launch_bounds__(RED_THREADS)
-cg_update_kernel(double* x, double* r, const double* p, const double* q, long N, double* part,
-                 KState* ks, double* hstat, const int* skip) {
-  if (skip && *skip) return;
-  __shared__ double red[16];
-  const double al = ks->alpha;
-  const int G = gridDim.x;
-  const long stride = (long)G * RED_THREADS;
-  double ss[1] = {0.0};
-  for (long e = (long)blockIdx.x * RED_THREADS + threadIdx.x; e < N; e += stride) {
-    x[e] += al * p[e];
-    const double rv = r[e] - al * q[e];
-    r[e] = rv;
-    ss[0] += rv * rv;
-  }
-  block_sum<1>(ss, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = ss[0];
-  if (!last_block(&ks->counter)) return;
-  __shared__ double tot[1];
-  reduce_parts(part, G, 1, tot);
-  if (threadIdx.x == 0) {
-    epilogue_norm(ks, EP_CG_R, 0, tot[0], hstat);
-    ks->counter = 0;
   }
 }
 
@@ -466,6 +570,45 @@ template <typename TI, typename TO>
 __global__ void cast_kernel(const TI* a, TO* out, long N) {
   const long stride = (long)gridDim.x * blockDim.x;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) out[e] = (TO)a[e];
+}
+
+// out (cols x rows) = in (rows x cols)^T, plus `addend` (same layout as out)
+// when ADD.  32 x 32 tiles through LDS: reads and writes are 256-byte row
+// segments (float64) and several workgroups share a CU.
+template <typename T, bool ADD>
+__global__ void __launch_bounds__(256)
+transpose_kernel(const T* __restrict__ in, T* __restrict__ out, int rows, int cols, const T* addend,
+                 const int* skip, const int* skip2) {
+  if (skipped(skip, skip2)) return;
+  __shared__ T tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  // unconditional loads at clamped offsets, so that all four are in flight together
+  T t[4], ad[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = min(r0 + ty + 8 * i, rows - 1), c = min(c0 + tx, cols - 1);
+    t[i] = in[(long)r * cols + c];
+  }
+  if (ADD) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int c = min(c0 + ty + 8 * i, cols - 1), r = min(r0 + tx, rows - 1);
+      ad[i] = addend[(long)c * rows + r];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) tile[ty + 8 * i][tx] = t[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int c = c0 + ty + 8 * i, r = r0 + tx;
+    if (c < cols && r < rows) {
+      T v = tile[tx][ty + 8 * i];
+      if (ADD) v += ad[i];
+      out[(long)c * rows + r] = v;
+    }
+  }
 }
 
 }  // namespace fde

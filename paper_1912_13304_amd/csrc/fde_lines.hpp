@@ -104,15 +104,31 @@ __device__ __forceinline__ void dftR(cx<T>* v) {
   else dft2(v);
 }
 
+// LDS layout of a line: element i at offset i; lines are P + 1 elements
+// apart.  (A padded layout that spreads the 128-byte lane strides of the
+// first Stockham writes over all banks was measured: it cost more in index
+// arithmetic than it saved in bank conflicts.)
+__device__ __forceinline__ int pidx(int i) { return i; }
+__host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v >> 1); }
+__host__ __device__ constexpr int line_stride(int P) { return P + 1; }
+
 // One Stockham pass of radix R over B lines of length P in LDS (line stride
 // LS complex elements).  Ls = product of the radices of earlier passes.
 // Butterfly j of a line reads x[j + r P/R], multiplies element r by
 // w^(r k) with k = j mod Ls and w = exp(-2 pi i/(Ls R)), applies DFT_R and
 // writes y[(j - k) R + k + r Ls].  In place: all reads finish before a
 // barrier, then all writes.
+// Twiddle w = exp(-i pi m/P) for 0 <= m < 2P from the LDS copy of its first
+// P entries (the second half is the negated first half).
+template <typename T>
+__device__ __forceinline__ cx<T> twiddle(const cx<T>* tw, int m, int P) {
+  const cx<T> t = tw[m < P ? m : m - P];
+  return m < P ? t : mk(-t.x, -t.y);
+}
+
 template <typename T, int EPT, int R>
 __device__ __forceinline__ void fft_pass(cx<T>* buf, int LS, int logPr, int Ls, int logR,
-                                         const cx<T>* __restrict__ W2, int twshift) {
+                                         const cx<T>* tw, int P, int twshift) {
   constexpr int NB = EPT / R;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int Pr = 1 << logPr;
@@ -126,7 +142,7 @@ __device__ __forceinline__ void fft_pass(cx<T>* buf, int LS, int logPr, int Ls, 
     base[s] = line * LS;
     jj[s] = j;
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[s][r] = buf[base[s] + j + r * Pr];
+    for (int r = 0; r < R; ++r) v[s][r] = buf[base[s] + pidx(j + r * Pr)];
   }
   __syncthreads();
 #pragma unroll
@@ -135,32 +151,44 @@ __device__ __forceinline__ void fft_pass(cx<T>* buf, int LS, int logPr, int Ls, 
     const int k = j & (Ls - 1);
     if (Ls > 1) {
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[s][r] = mul(v[s][r], W2[(r * k) << twshift]);
+      for (int r = 1; r < R; ++r) v[s][r] = mul(v[s][r], twiddle(tw, (r * k) << twshift, P));
     }
     dftR<T, R>(v[s]);
-    const int o = base[s] + ((j - k) << logR) + k;
+    const int o = ((j - k) << logR) + k;
 #pragma unroll
-    for (int r = 0; r < R; ++r) buf[o + r * Ls] = v[s][r];
+    for (int r = 0; r < R; ++r) buf[base[s] + pidx(o + r * Ls)] = v[s][r];
   }
   __syncthreads();
+}
+
+// Compile-time pass sequence (radix 8, then 4 or 2) for P = 2^LOGP.
+template <typename T, int EPT, int LOGP, int LOGLS>
+__device__ __forceinline__ void fft_lines_ct(cx<T>* buf, int LS, const cx<T>* tw) {
+  if constexpr (LOGLS < LOGP) {
+    constexpr int REM = LOGP - LOGLS;
+    constexpr int LOGR = REM >= 3 ? 3 : REM;
+    fft_pass<T, EPT, (1 << LOGR)>(buf, LS, LOGP - LOGR, 1 << LOGLS, LOGR, tw, 1 << LOGP, LOGP + 1 - LOGLS - LOGR);
+    fft_lines_ct<T, EPT, LOGP, LOGLS + LOGR>(buf, LS, tw);
+  }
 }
 
 // Forward FFT of length P = 2^logP on every line in LDS.  The caller has
 // synchronised after writing the input; results are visible on return.
 template <typename T, int EPT>
-__device__ __forceinline__ void fft_lines(cx<T>* buf, int LS, int logP, const cx<T>* __restrict__ W2) {
+__device__ __forceinline__ void fft_lines(cx<T>* buf, int LS, int logP, const cx<T>* tw) {
+  const int P = 1 << logP;
   int logLs = 0;
   while (logLs < logP) {
     const int rem = logP - logLs;
     const int Ls = 1 << logLs;
     if (rem >= 3) {
-      fft_pass<T, EPT, 8>(buf, LS, logP - 3, Ls, 3, W2, logP + 1 - logLs - 3);
+      fft_pass<T, EPT, 8>(buf, LS, logP - 3, Ls, 3, tw, P, logP + 1 - logLs - 3);
       logLs += 3;
     } else if (rem == 2) {
-      fft_pass<T, EPT, 4>(buf, LS, logP - 2, Ls, 2, W2, logP + 1 - logLs - 2);
+      fft_pass<T, EPT, 4>(buf, LS, logP - 2, Ls, 2, tw, P, logP + 1 - logLs - 2);
       logLs += 2;
     } else {
-      fft_pass<T, EPT, 2>(buf, LS, logP - 1, Ls, 1, W2, logP + 1 - logLs - 1);
+      fft_pass<T, EPT, 2>(buf, LS, logP - 1, Ls, 1, tw, P, logP + 1 - logLs - 1);
       logLs += 1;
     }
   }
@@ -194,6 +222,7 @@ struct LineArgs {
   const cx<T>* W2;    // exp(-2 pi i m/(2P)), m < 2P
   const cx<T>* lam;   // circulant eigenvalues, bins 0..P
   const int* skip;    // nonzero: the kernel returns at once
+  const int* skip2;   // second flag with the same meaning
   long ls, es;        // line stride and element stride in the vectors
   int n, P, logP, nlines, B, logB, LS, ntiles;
 };
@@ -207,21 +236,34 @@ __device__ __forceinline__ int xcd_tile(int ntiles) {
   return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
 }
 
-template <typename T, bool COLS, int FL>
+// LOGP > 0: transform size fixed at compile time (P = 2^LOGP, B = max(1,
+// 512/P) lines per workgroup), so that pass radices, strides, twiddle
+// indices and LDS offsets are constants; LOGP = 0 reads them from `a`.
+template <typename T, bool COLS, int FL, int LOGP>
 __global__ void __launch_bounds__(512) line_kernel(LineArgs<T> a) {
   constexpr int EPT = 8;
-  if (a.skip && *a.skip) return;
+  if ((a.skip && *a.skip) || (a.skip2 && *a.skip2)) return;
   const int tile = xcd_tile(a.ntiles);
   if (tile >= a.ntiles) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
 
-  const int tid = threadIdx.x, nth = blockDim.x;
-  const int P = a.P, logP = a.logP, n = a.n, LS = a.LS;
-  const int line0 = tile * a.B;
+  constexpr int CP = LOGP > 0 ? (1 << LOGP) : 0;
+  constexpr int CB = LOGP > 0 ? (CP >= 512 ? 1 : 512 / CP) : 0;
+  const int logP = LOGP > 0 ? LOGP : a.logP;
+  const int P = LOGP > 0 ? CP : a.P;
+  const int B = LOGP > 0 ? CB : a.B;
+  const int logB = LOGP > 0 ? ilog2c(CB) : a.logB;
+  const int LS = LOGP > 0 ? line_stride(CP) : a.LS;
+  const int nth = LOGP > 0 ? CB * CP / EPT : (int)blockDim.x;
+  const int tid = threadIdx.x;
+  const int n = a.n;
+  const int line0 = tile * B;
+  // LDS: B line buffers, 2B side entries, B*P twiddle slots (the first P used)
+  cx<T>* tw = buf + B * LS + 2 * B;
 
   int li[EPT], mi[EPT];
-  long gi[EPT];
+  int gi[EPT];   // element offsets (N < 2^31); 0 for padding/out-of-range slots
   bool ok[EPT];
   T v[EPT];
 #pragma unroll
@@ -229,8 +271,8 @@ __global__ void __launch_bounds__(512) line_kernel(LineArgs<T> a) {
     const int e = tid + i * nth;
     int l, m;
     if (COLS) {
-      l = e & (a.B - 1);
-      m = e >> a.logB;
+      l = e & (B - 1);
+      m = e >> logB;
     } else {
       l = e >> logP;
       m = e & (P - 1);
@@ -238,48 +280,83 @@ __global__ void __launch_bounds__(512) line_kernel(LineArgs<T> a) {
     li[i] = l;
     mi[i] = m;
     ok[i] = (m < n) && (line0 + l < a.nlines);
-    gi[i] = (long)(line0 + l) * a.ls + (long)m * a.es;
+    gi[i] = ok[i] ? (line0 + l) * (int)a.ls + m * (int)a.es : 0;
   }
+  // Every global operand of this thread is loaded here, unconditionally (at
+  // a valid offset) and before any use, so that all loads are in flight
+  // together and their latency overlaps the transforms below.
+  T xpre[EPT], xpost[EPT], xcp[EPT], xcm[EPT], xb[EPT], xf[EPT];
+  T twr[8], twi[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const cx<T> t = a.W2[(tid + k * nth) & (P - 1)];
+    twr[k] = t.x;
+    twi[k] = t.y;
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    v[i] = a.in[gi[i]];
+    if (a.pre) xpre[i] = a.pre[gi[i]];
+    if (a.post) xpost[i] = a.post[gi[i]];
+    if (FL & LF_FDST2) {
+      const int ln = line0 + li[i] < a.nlines ? line0 + li[i] : 0;
+      xf[i] = a.fline[ln] + a.felem[mi[i] < n ? mi[i] : 0];
+    }
+    if (FL & LF_TOEP) {
+      xcp[i] = a.cplus[gi[i]];
+      xcm[i] = a.cminus[gi[i]];
+    }
+    if (FL & LF_EXTBASE) xb[i] = a.base[gi[i]];
+  }
+  // keep the scheduler from interleaving the LDS stores (which wait for
+  // their load) with the loads above
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) tw[tid + k * nth] = mk(twr[k], twi[k]);   // B*P >= P slots
   {
-    const T s = a.sc ? (T)(*a.sc) : T(1);
+    const T sc = a.sc ? (T)(*a.sc) : T(1);
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      T x = T(0);
-      if (ok[i]) {
-        x = a.in[gi[i]] * s;
-        if (a.pre) x *= a.pre[gi[i]];
-      }
-      v[i] = x;
+      T x = v[i] * sc;
+      if (a.pre) x *= xpre[i];
+      v[i] = ok[i] ? x : T(0);
     }
   }
 
   const T rs2P = T(1) / sqrt(T(2 * P));
+  auto FFT = [&]() {
+    if constexpr (LOGP > 0) fft_lines_ct<T, EPT, LOGP, 0>(buf, LS, tw);
+    else fft_lines<T, EPT>(buf, LS, logP, tw);
+  };
+  T* bufr = reinterpret_cast<T*>(buf);
+  // real view: f_u of line l is component (u & 1) of complex element u >> 1
+  auto rset = [&](int l, int u, T val) { bufr[2 * (l * LS + pidx(u >> 1)) + (u & 1)] = val; };
+  auto cget = [&](int l, int i) -> cx<T> { return buf[l * LS + pidx(i)]; };
 
   // ---- DST-I: v <- S_n v --------------------------------------------------
   auto dst = [&]() {
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      T* f = reinterpret_cast<T*>(buf + li[i] * LS);   // f[u] = u_u, u < 2P
-      const int m = mi[i];
+      const int m = mi[i];   // f_u = u_u, the odd extension, u < 2P
       if (m < n) {
-        f[m + 1] = v[i];
-        f[2 * P - m - 1] = -v[i];
+        rset(li[i], m + 1, v[i]);
+        rset(li[i], 2 * P - m - 1, -v[i]);
       } else {
-        f[0] = T(0);
-        f[P] = T(0);
+        rset(li[i], 0, T(0));
+        rset(li[i], P, T(0));
       }
     }
     __syncthreads();
-    fft_lines<T, EPT>(buf, LS, logP, a.W2);
+    FFT();
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const int m = mi[i];
       if (m < n) {
         const int k = m + 1;
-        const cx<T> zk = buf[li[i] * LS + k];
-        const cx<T> zn = buf[li[i] * LS + P - k];
-        const cx<T> w = a.W2[k];            // cos(pi k/P) - i sin(pi k/P)
+        const cx<T> zk = cget(li[i], k);
+        const cx<T> zn = cget(li[i], P - k);
+        const cx<T> w = tw[k];              // cos(pi k/P) - i sin(pi k/P)
         const T imU = T(0.5) * ((zk.y - zn.y) - w.x * (zk.x - zn.x) + w.y * (zk.y + zn.y));
         v[i] = -imU * rs2P;
       }
@@ -290,13 +367,13 @@ __global__ void __launch_bounds__(512) line_kernel(LineArgs<T> a) {
   if (FL & LF_FDST2) {
 #pragma unroll
     for (int i = 0; i < EPT; ++i)
-      if (mi[i] < n) v[i] = v[i] / (a.fline[line0 + li[i] < a.nlines ? line0 + li[i] : 0] + a.felem[mi[i]]);
+      if (mi[i] < n) v[i] = v[i] / xf[i];
     dst();
   }
   if (a.post) {
 #pragma unroll
     for (int i = 0; i < EPT; ++i)
-      if (ok[i]) v[i] *= a.post[gi[i]];
+      if (ok[i]) v[i] *= xpost[i];
   }
   if (FL & LF_STOREZ) {
 #pragma unroll
@@ -314,13 +391,12 @@ __global__ void __launch_bounds__(512) line_kernel(LineArgs<T> a) {
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    T* f = reinterpret_cast<T*>(buf + li[i] * LS);   // f[u] = p_u, the zero-padded v
-    const int m = mi[i];
-    f[m] = (m < n) ? v[i] : T(0);
-    f[P + m] = T(0);
+    const int m = mi[i];   // f_u = p_u, the zero-padded v, u < 2P
+    rset(li[i], m, (m < n) ? v[i] : T(0));
+    rset(li[i], P + m, T(0));
   }
   __syncthreads();
-  fft_lines<T, EPT>(buf, LS, logP, a.W2);
+  FFT();
 
   // Pair phase: bins k and P-k of the packed spectrum Q give the half
   // spectrum of the real sequence, Pk = E + w O, P(P-k) = conj(E - w O),
@@ -344,9 +420,8 @@ __global__ void __launch_bounds__(512) line_kernel(LineArgs<T> a) {
     const int k = p & (H - 1);
     pl[s] = l;
     pk[s] = k;
-    const cx<T>* q = buf + l * LS;
     if (k == 0) {
-      const cx<T> q0 = q[0];
+      const cx<T> q0 = cget(l, 0);
       const T p0 = q0.x + q0.y, pP = q0.x - q0.y;
       const cx<T> l0 = a.lam[0], lP = a.lam[P];
       const cx<T> one = mk(T(1), T(0));
@@ -356,10 +431,10 @@ __global__ void __launch_bounds__(512) line_kernel(LineArgs<T> a) {
       yP = scale(conj(lP), pP);
       w2[s][0] = winv(y0, yP, one);
     } else {
-      const cx<T> qk = q[k], qn = q[P - k];
+      const cx<T> qk = cget(l, k), qn = cget(l, P - k);
       const cx<T> E = scale(add(qk, conj(qn)), T(0.5));
       const cx<T> O = mul_mi(scale(sub(qk, conj(qn)), T(0.5)));
-      const cx<T> w = a.W2[k];
+      const cx<T> w = tw[k];
       const cx<T> wO = mul(w, O);
       const cx<T> pkv = add(E, wO);
       const cx<T> pnv = conj(sub(E, wO));
@@ -376,9 +451,9 @@ __global__ void __launch_bounds__(512) line_kernel(LineArgs<T> a) {
   }
   // self-paired bin k = P/2 (one per line), w = exp(-i pi/2) = -i; its two
   // spectra go to a side buffer of 2B entries after the line buffers
-  cx<T>* sbuf = buf + a.B * LS;
-  for (int l = tid; l < a.B; l += nth) {
-    const cx<T> q = buf[l * LS + H];
+  cx<T>* sbuf = buf + B * LS;
+  for (int l = tid; l < B; l += nth) {
+    const cx<T> q = cget(l, H);
     const cx<T> ph = conj(q);   // E + w O with E = Re q, O = Im q, w = -i
     const cx<T> lh = a.lam[H];
     const cx<T> w = mk(T(0), T(-1));
@@ -393,14 +468,14 @@ __global__ void __launch_bounds__(512) line_kernel(LineArgs<T> a) {
     for (int s = 0; s < NPR; ++s) {
       cx<T>* q = buf + pl[s] * LS;
       const int k = pk[s];
-      q[k] = conj(wr[s][0]);
-      if (k != 0) q[P - k] = conj(wr[s][1]);
+      q[pidx(k)] = conj(wr[s][0]);
+      if (k != 0) q[pidx(P - k)] = conj(wr[s][1]);
     }
-    for (int l = tid; l < a.B; l += nth) buf[l * LS + H] = sbuf[2 * l + which];
+    for (int l = tid; l < B; l += nth) buf[l * LS + pidx(H)] = sbuf[2 * l + which];
   };
   put(w1, 0);
   __syncthreads();
-  fft_lines<T, EPT>(buf, LS, logP, a.W2);
+  FFT();
   const T invP = T(1) / T(P);
   T acc[EPT];
 #pragma unroll
@@ -408,23 +483,23 @@ __global__ void __launch_bounds__(512) line_kernel(LineArgs<T> a) {
     acc[i] = T(0);
     const int m = mi[i];
     if (ok[i]) {
-      const cx<T> r = buf[li[i] * LS + (m >> 1)];
+      const cx<T> r = cget(li[i], m >> 1);
       const T y = ((m & 1) ? -r.y : r.x) * invP;
-      acc[i] = a.cplus[gi[i]] * y;
+      acc[i] = xcp[i] * y;
     }
   }
   __syncthreads();
   put(w2, 1);
   __syncthreads();
-  fft_lines<T, EPT>(buf, LS, logP, a.W2);
+  FFT();
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int m = mi[i];
     if (ok[i]) {
-      const cx<T> r = buf[li[i] * LS + (m >> 1)];
+      const cx<T> r = cget(li[i], m >> 1);
       const T y = ((m & 1) ? -r.y : r.x) * invP;
-      acc[i] += a.cminus[gi[i]] * y;
-      const T b = (FL & LF_EXTBASE) ? a.base[gi[i]] : v[i];
+      acc[i] += xcm[i] * y;
+      const T b = (FL & LF_EXTBASE) ? xb[i] : v[i];
       a.out[gi[i]] = a.bscale * b + a.tscale * acc[i];
     }
   }
