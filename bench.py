@@ -40,9 +40,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=1023)
     ap.add_argument("--tsteps", type=int, default=10)
-    ap.add_argument("--inner", type=int, default=8)
+    ap.add_argument("--inner", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--forms", default="fp64,mixed")
+    ap.add_argument("--quick", action="store_true",
+                    help="skip the per-class sampling pass; probe --probe-class in the timed region")
+    ap.add_argument("--probe-class", default="line32_dst_storez_toeplitz")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is a design "
@@ -95,20 +98,28 @@ def main():
         log(f"[bench] warmup {name} x{args.warmup}")
         for _ in range(args.warmup):
             job(kw)
-        # one untimed job per kernel class: share of GPU time per class
+        # one untimed job per kernel class: sampled GPU time of each candidate
+        # (every 8th launch of the class is bracketed with HIP events)
         shares = {}
-        for cls_name, cls in (("maxpy64", fde.PROBE_MAXPY64), ("mdot64", fde.PROBE_MDOT64),
-                              ("line64", fde.PROBE_LINE64), ("line32", fde.PROBE_LINE32),
-                              ("maxpy32", fde.PROBE_MAXPY32), ("mdot32", fde.PROBE_MDOT32)):
+        cands = [("cgs_dot64", fde.PROBE_MDOT64), ("cgs_update64", fde.PROBE_MAXPY64),
+                 ("cgs_dot32", fde.PROBE_MDOT32), ("cgs_update32", fde.PROBE_MAXPY32)]
+        for fl, pname in fde.LINE_PROGRAMS.items():
+            cands.append((f"line64_{pname}", fde.PROBE_LINE64_VARIANT + fl))
+            cands.append((f"line32_{pname}", fde.PROBE_LINE32_VARIANT + fl))
+        if args.quick:
+            cands = [c for c in cands if c[0] == args.probe_class] or cands[:1]
+        for cls_name, cls in cands:
             _, pr, _ = job(kw, probe=cls)
             ms, nl, by = pr
             if nl:
                 shares[cls_name] = dict(ms=ms, launches=nl, bytes=by, GBps=by / (ms * 1e-3) / 1e9 if ms else 0.0,
-                                        cls=cls)
+                                        cls=cls, avg_us=1e3 * ms / nl)
+        if not shares:
+            shares = {cands[0][0]: dict(ms=0.0, launches=0, bytes=0.0, GBps=0.0, cls=cands[0][1], avg_us=0.0)}
         dom = max(shares, key=lambda k: shares[k]["ms"])
         dominant[name] = dom
-        log(f"[bench] {name} kernel classes: " + ", ".join(f"{k}: {v['ms']:.2f} ms {v['GBps']:.0f} GB/s"
-                                                          for k, v in shares.items()))
+        log(f"[bench] {name} sampled kernel classes: " + ", ".join(
+            f"{k}: {v['ms']:.2f} ms, {v['avg_us']:.1f} us/launch, {v['GBps']:.0f} GB/s" for k, v in shares.items()))
         # timed region: K whole jobs, the dominant kernel class probed with HIP events
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -128,8 +139,8 @@ def main():
             inner_iters_per_solve=float(np.mean([i["inner_iters"] for inf in all_infos for i in inf])),
             max_relres=float(max(i["relres_true"] for inf in all_infos for i in inf)),
             all_converged=all(i["converged"] for inf in all_infos for i in inf),
-            kernel_classes={k: dict(ms_per_job=v["ms"], GBps=v["GBps"], launches=v["launches"])
-                            for k, v in shares.items()},
+            kernel_classes_sampled={k: dict(ms=v["ms"], avg_us=v["avg_us"], GBps=v["GBps"],
+                                            launches=v["launches"]) for k, v in shares.items()},
             dominant=dict(cls=dom, ms=probe_tot[0], launches=probe_tot[1], bytes=probe_tot[2]),
         )
         log(f"[bench] {name}: {results[name]['solves_per_s']:.1f} solves/s, "

@@ -106,7 +106,7 @@ typedef struct {
 
 /* Fills `p` with: 1D, n = 1023, alpha = 1.5 on (0,2), dt = h, FDE_W_SHIFTED,
    FDE_T_EULER, FDE_P_TAU, FDE_D_LEFT, shift = NaN, FDE_S_GMRES, restart 30,
-   maxit 10000, tol 1e-8, FDE_FP64, inner_steps 8. */
+   maxit 10000, tol 1e-8, FDE_FP64, inner_steps 16. */
 void fde_default_params(fde_params* p);
 
 /* Builds a plan for M and P (setup row of the method: Grunwald weights
@@ -149,19 +149,24 @@ size_t fde_plan_bytes(const fde_params* p);
 void fde_destroy(fde_plan plan);
 
 /* Kernel timing probe (benchmarking).  fde_probe(plan, cls) starts bracketing
-   every launch of one kernel class issued by this plan with HIP events on the
-   launch stream, and accumulates the launch's algorithmic bytes (each vector
-   operand read or written once); cls = FDE_PROBE_OFF stops.  fde_probe_read
-   synchronises on the recorded events and returns the summed kernel time in
-   milliseconds, the number of launches and the summed algorithmic bytes, then
-   clears the record.  Either pointer argument may be NULL. */
+   every 8th launch of one kernel class issued by this plan with HIP events on
+   the launch stream (a sample keeps the event overhead out of the timing),
+   and accumulates those launches' algorithmic bytes (each vector operand read
+   or written once); cls = FDE_PROBE_OFF stops.  fde_probe_read synchronises
+   on the recorded events and returns the summed time of the bracketed
+   launches in milliseconds, their number and their summed algorithmic bytes,
+   then clears the record.  Either pointer argument may be NULL. */
 enum { FDE_PROBE_OFF = 0,
        FDE_PROBE_MAXPY64 = 1,   /* float64 multi-vector update w -= sum c_i V_i (Gram-Schmidt) */
        FDE_PROBE_MDOT64 = 2,    /* float64 multi-dot V^T w                                       */
        FDE_PROBE_LINE64 = 3,    /* float64 line transforms (DST-I / Toeplitz passes)            */
        FDE_PROBE_LINE32 = 4,    /* float32 line transforms                                       */
        FDE_PROBE_MAXPY32 = 5,
-       FDE_PROBE_MDOT32 = 6 };
+       FDE_PROBE_MDOT32 = 6,
+       FDE_PROBE_CGS64 = 7,     /* every float64 Gram-Schmidt pass (dot, update+dot, update+norm) */
+       FDE_PROBE_CGS32 = 8,
+       FDE_PROBE_LINE64_VARIANT = 64,   /* + line program flags (0..31): one float64 line kernel   */
+       FDE_PROBE_LINE32_VARIANT = 96 }; /* + line program flags (0..31): one float32 line kernel   */
 fde_status fde_probe(fde_plan plan, int cls);
 fde_status fde_probe_read(fde_plan plan, double* ms, long long* launches, double* bytes);
 

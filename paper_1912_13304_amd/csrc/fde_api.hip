@@ -91,6 +91,8 @@ struct fde_plan_s {
   hipEvent_t ev[4] = {};
   // timing probe
   int probe = FDE_PROBE_OFF;
+  long long pseen = 0;              // launches of the probed class since fde_probe
+  static constexpr int PSTRIDE = 8; // every PSTRIDE-th launch is bracketed
   std::vector<hipEvent_t> pev;      // event pool, pairs (start, stop)
   size_t pused = 0;                 // pairs recorded since the last read
   double pbytes = 0.0;
@@ -139,7 +141,7 @@ void fde_default_params_impl(fde_params* p) {
   p->maxit = 10000;
   p->tol = 1e-8;
   p->precision = FDE_FP64;
-  p->inner_steps = 8;
+  p->inner_steps = 16;
 }
 
 extern "C" void fde_default_params(fde_params* p) {
@@ -561,7 +563,11 @@ struct ProbeScope {
   fde_plan pl;
   hipStream_t st;
   bool on;
-  ProbeScope(fde_plan p, int cls, hipStream_t s, double bytes) : pl(p), st(s), on(p && p->probe == cls && cls != 0) {
+  // cls: the launch's class; cls2: a second class it also belongs to (or 0)
+  ProbeScope(fde_plan p, int cls, hipStream_t s, double bytes, int cls2 = 0)
+      : pl(p), st(s), on(p && cls != 0 && (p->probe == cls || (cls2 != 0 && p->probe == cls2))) {
+    if (!on) return;
+    on = (pl->pseen++ % fde_plan_s::PSTRIDE) == 0;   // sample: keeps the event overhead small
     if (!on) return;
     if (pl->pev.size() < 2 * (pl->pused + 1)) {
       for (int i = 0; i < 2; ++i) {
@@ -585,8 +591,10 @@ struct ProbeScope {
 
 extern "C" fde_status fde_probe(fde_plan pl, int cls) {
   if (!pl) return fail(FDE_EINVAL, "NULL plan");
-  if (cls < FDE_PROBE_OFF || cls > FDE_PROBE_MDOT32) return fail(FDE_EINVAL, "bad probe class %d", cls);
+  if (cls < FDE_PROBE_OFF || cls >= 128 || (cls > FDE_PROBE_CGS32 && cls < FDE_PROBE_LINE64_VARIANT))
+    return fail(FDE_EINVAL, "bad probe class %d", cls);
   pl->probe = cls;
+  pl->pseen = 0;
   return FDE_OK;
 }
 
@@ -647,8 +655,8 @@ static void launch_line(const Dir& d, LineArgs<T> a, hipStream_t st) {
   const int nvec = (a.in != nullptr) + (a.pre != nullptr) + (a.post != nullptr) + (a.zout != nullptr) +
                    ((FL & LF_TOEP) ? 2 : 0) + ((FL & LF_EXTBASE) ? 1 : 0) + 1;
   const double bytes = (double)nvec * (double)d.n * (double)d.nlines * sizeof(T);
-  ProbeScope ps(g_probe_plan ? g_probe_plan : nullptr, sizeof(T) == 8 ? FDE_PROBE_LINE64 : FDE_PROBE_LINE32, st,
-                bytes);
+  ProbeScope ps(g_probe_plan, sizeof(T) == 8 ? FDE_PROBE_LINE64 : FDE_PROBE_LINE32, st, bytes,
+                (sizeof(T) == 8 ? FDE_PROBE_LINE64_VARIANT : FDE_PROBE_LINE32_VARIANT) + FL);
   switch (d.logP) {
     case 3: launch_line_k<T, FL, 3>(d, a, grid, nth, lds, st); break;
     case 4: launch_line_k<T, FL, 4>(d, a, grid, nth, lds, st); break;
@@ -936,18 +944,8 @@ static int red_grid(long N, long per) {
 static void finalize(fde_plan pl, int G, int nq, KState* ks, int fkind, int emode, int col, double* hstat,
                      hipStream_t st, const int* skip, const int* skip2) {
   if (G <= 1) return;
-  if (nq <= 1)
-    hipLaunchKernelGGL(finalize_kernel<1>, dim3(1), dim3(RED_THREADS), 0, st, pl->part, G, nq, ks, fkind, emode,
-                       col, hstat, skip, skip2);
-  else if (nq <= 8)
-    hipLaunchKernelGGL(finalize_kernel<8>, dim3(1), dim3(RED_THREADS), 0, st, pl->part, G, nq, ks, fkind, emode,
-                       col, hstat, skip, skip2);
-  else if (nq <= 16)
-    hipLaunchKernelGGL(finalize_kernel<16>, dim3(1), dim3(RED_THREADS), 0, st, pl->part, G, nq, ks, fkind, emode,
-                       col, hstat, skip, skip2);
-  else
-    hipLaunchKernelGGL(finalize_kernel<32>, dim3(1), dim3(RED_THREADS), 0, st, pl->part, G, nq, ks, fkind, emode,
-                       col, hstat, skip, skip2);
+  hipLaunchKernelGGL(finalize_kernel, dim3(fkind == FK_H ? nq : 1), dim3(RED_THREADS), 0, st, pl->part, G, nq, ks,
+                     fkind, emode, col, hstat, skip, skip2);
 }
 
 // ||a - b||^2 with an epilogue; out = a - b when out != null.
@@ -969,7 +967,7 @@ static void cgs_launch(fde_plan pl, const T* V, int k, T* w, KState* ks, int emo
                                  : (MODE == CG_DOT ? FDE_PROBE_MDOT32 : FDE_PROBE_MAXPY32);
   const double bytes = (double)(k + (MODE == CG_DOT ? 1 : 2)) * N * sizeof(T);
   {
-    ProbeScope ps(pl, cls, st, bytes);
+    ProbeScope ps(pl, cls, st, bytes, sizeof(T) == 8 ? FDE_PROBE_CGS64 : FDE_PROBE_CGS32);
     hipLaunchKernelGGL((cgs_kernel<T, KC, EPI, MODE>), dim3(G), dim3(RED_THREADS), 0, st, V, N, k, w, w, N, emode,
                        col, pl->part, ks, hstat, skip, skip2);
   }
@@ -980,9 +978,11 @@ static void cgs_launch(fde_plan pl, const T* V, int k, T* w, KState* ks, int emo
 template <typename T, int MODE>
 static void cgs_pass(fde_plan pl, const T* V, int k, T* w, KState* ks, int emode, int col, double* hstat,
                      hipStream_t st, const int* skip, const int* skip2) {
-  if (k <= 8) cgs_launch<T, 8, 4, MODE>(pl, V, k, w, ks, emode, col, hstat, st, skip, skip2);
-  else if (k <= 16) cgs_launch<T, 16, 2, MODE>(pl, V, k, w, ks, emode, col, hstat, st, skip, skip2);
-  else cgs_launch<T, 32, 1, MODE>(pl, V, k, w, ks, emode, col, hstat, st, skip, skip2);
+  // (twice the elements per thread for float32 was measured slower: fewer workgroups)
+  constexpr int X = 1;
+  if (k <= 8) cgs_launch<T, 8, 4 * X, MODE>(pl, V, k, w, ks, emode, col, hstat, st, skip, skip2);
+  else if (k <= 16) cgs_launch<T, 16, 2 * X, MODE>(pl, V, k, w, ks, emode, col, hstat, st, skip, skip2);
+  else cgs_launch<T, 32, 1 * X, MODE>(pl, V, k, w, ks, emode, col, hstat, st, skip, skip2);
 }
 
 // CGS2 of w (= basis slot j+1) against basis vectors 0..j, then the Givens

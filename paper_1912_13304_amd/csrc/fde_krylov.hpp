@@ -275,27 +275,30 @@ __device__ inline void publish_or_finish(double* tot, int nq, double* part, KSta
   for (int q = threadIdx.x; q < nq; q += blockDim.x) part[(size_t)q * gridDim.x + blockIdx.x] = tot[q];
 }
 
-// One-workgroup finalize: tot[q] = sum_b part[q*G + b] for q < nq <= KC, in a
-// fixed order, then the scalar epilogue.  Thread t adds partials b = t,
-// t + 256, ... of every value (coalesced, all loads independent), and the
-// workgroup butterfly reduction finishes.
-template <int KC>
+// Finalize of a reduction.  Workgroup q adds the G partials of value q in a
+// fixed order (thread t takes b = t, t + 256, ...; a butterfly finishes).
+// FK_H: one workgroup per Gram-Schmidt coefficient, each stores its own h_q
+// and c_q.  FK_NORM / FK_DOT: a single value, then the scalar epilogue.
 __global__ void __launch_bounds__(RED_THREADS)
 finalize_kernel(const double* part, int G, int nq, KState* ks, int fkind, int emode, int col, double* hstat,
                 const int* skip, const int* skip2) {
   if (skipped(skip, skip2)) return;
-  __shared__ double red[16 * KC];
-  __shared__ double tot[KC];
-  double acc[KC];
-#pragma unroll
-  for (int q = 0; q < KC; ++q) acc[q] = 0.0;
-  for (int b = threadIdx.x; b < G; b += RED_THREADS) {
-#pragma unroll
-    for (int q = 0; q < KC; ++q)
-      if (q < nq) acc[q] += part[(size_t)q * G + b];
+  __shared__ double red[16];
+  __shared__ double tot[1];
+  const int q = blockIdx.x;
+  double acc[1] = {0.0};
+  for (int b = threadIdx.x; b < G; b += RED_THREADS) acc[0] += part[(size_t)q * G + b];
+  block_multi_sum<1>(acc, red, tot);
+  if (fkind == FK_H) {
+    if (threadIdx.x == 0) {
+      const bool second = emode == EP_H2;
+      const double hq = ks->scale[q] * tot[0];
+      (second ? ks->h2 : ks->h1)[q] = hq;
+      (second ? ks->c2 : ks->c1)[q] = ks->scale[q] * hq;
+    }
+  } else {
+    finish(tot, 1, ks, fkind, emode, col, hstat);
   }
-  block_multi_sum<KC>(acc, red, tot);
-  finish(tot, nq, ks, fkind, emode, col, hstat);
 }
 
 // Classical Gram-Schmidt passes against the k <= KC basis vectors of V

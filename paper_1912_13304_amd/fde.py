@@ -25,7 +25,11 @@ D_LEFT, D_RIGHT = 0, 1
 S_GMRES, S_PCG = 0, 1
 FP64, MIXED = 0, 1
 
-PROBE_OFF, PROBE_MAXPY64, PROBE_MDOT64, PROBE_LINE64, PROBE_LINE32, PROBE_MAXPY32, PROBE_MDOT32 = range(7)
+PROBE_OFF, PROBE_MAXPY64, PROBE_MDOT64, PROBE_LINE64, PROBE_LINE32, PROBE_MAXPY32, PROBE_MDOT32, PROBE_CGS64, PROBE_CGS32 = range(9)
+PROBE_LINE64_VARIANT, PROBE_LINE32_VARIANT = 64, 96
+# line program flags (fde_lines.hpp): DST1 = 1, FDST2 = 2, STOREZ = 4, TOEP = 8, EXTBASE = 16
+LINE_PROGRAMS = {1: "dst", 3: "dst_f_dst", 8: "toeplitz", 11: "dst_f_dst_toeplitz", 12: "storez_toeplitz",
+                 13: "dst_storez_toeplitz", 15: "dst_f_dst_storez_toeplitz"}
 
 EXPORTED = ["fde_default_params", "fde_assemble", "fde_matvec", "fde_tau_apply", "fde_solve", "fde_rhs",
             "fde_plan_bytes", "fde_destroy", "fde_last_error", "fde_probe", "fde_probe_read"]
