@@ -46,6 +46,9 @@ def main():
     ap.add_argument("--quick", action="store_true",
                     help="skip the per-class sampling pass; probe --probe-class in the timed region")
     ap.add_argument("--probe-class", default="line32_dst_storez_toeplitz")
+    ap.add_argument("--serve-rate", type=float, default=500.0, help="Poisson arrival rate of the served leg")
+    ap.add_argument("--serve-count", type=int, default=32, help="requests in the served leg (0: skip)")
+    ap.add_argument("--serve-slots", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is a design "
@@ -146,6 +149,20 @@ def main():
         log(f"[bench] {name}: {results[name]['solves_per_s']:.1f} solves/s, "
             f"{results[name]['ms_per_solve']:.2f} ms/solve, {results[name]['iters_per_solve']:.1f} it/solve")
 
+    # served leg: Poisson arrivals of mixed 1D / 2D time-stepping requests,
+    # continuous batching over slots x streams, mixed precision
+    served = None
+    if args.serve_count > 0:
+        from paper_1912_13304_amd import serve
+        arr = fi.served_stream(args.serve_rate, args.serve_count, seed=5, n1d=(1023, 4095))
+        serve.serve_stream(arr[:4], slots=args.serve_slots, precision=fde.MIXED, inner_steps=args.inner)  # warm
+        res, wall = serve.serve_stream(arr, slots=args.serve_slots, precision=fde.MIXED, inner_steps=args.inner)
+        served = serve.latency_stats(res)
+        served.update(rate_req_per_s=args.serve_rate, slots=args.serve_slots,
+                      mix="70% 1D n in [1023, 4095] (2^k-1), 30% 2D n in {127,255,511,1023}; 5-50 steps; "
+                          "alpha ~ U(1.1,1.9); mixed precision, tol 1e-8")
+        log(f"[bench] served: {served}")
+
     # plain copy bandwidth on the same GPU (1 GiB read + 1 GiB write)
     src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
     dst = torch.empty_like(src)
@@ -211,6 +228,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": d["cls"],
                      "avg_launch_us": avg_us, "copy_GBps": copy_gbs},
+        "served": served,
+        "p99_served_latency_ms": served["p99_ms"] if served else None,
         "cpu_baseline": cpu,
         "parity": parity,
     }

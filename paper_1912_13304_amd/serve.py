@@ -1,0 +1,179 @@
+"""Continuous-batching server for time-stepping FDE solves on one GPU.
+
+Requests are whole implicit time-stepping jobs (a ``fde_inputs.Problem``:
+coefficients, initial state, number of steps).  The server keeps a fixed
+number of slots; each slot owns a HIP stream and a host worker thread that
+drives the C ABI (ctypes releases the GIL during each call, so the workers
+enqueue concurrently).  A request is admitted as soon as a slot is free and
+its HBM footprint (``fde_plan_bytes`` plus its state vectors) fits the
+budget; requests that arrive while others are on the GPU therefore start
+while those are still running, and their kernels overlap on the device.
+Per-request state stays on the device for the whole job: the plan (symbol
+samples, circulant eigenvalues, twiddles, coefficients, Krylov workspace)
+and the current and previous time levels.
+
+Results do not depend on the mix: every reduction in the library sums in a
+fixed order within one solve, so a request's iterates are the same alone and
+in any mix.
+"""
+from __future__ import annotations
+
+import threading
+import time
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+from . import fde
+
+
+@dataclass
+class Result:
+    name: str
+    arrival: float          # seconds since the stream started
+    start: float            # admission time
+    finish: float           # completion time
+    steps: int
+    iters: List[int] = field(default_factory=list)
+    inner_iters: List[int] = field(default_factory=list)
+    relres: List[float] = field(default_factory=list)
+    u: Optional[object] = None   # final state (device tensor) when keep_state
+
+    @property
+    def latency(self) -> float:
+        return self.finish - self.arrival
+
+
+def footprint(problem, **kw) -> int:
+    """HBM bytes a request holds while it runs: the plan plus three state vectors."""
+    p = fde.params_for(problem, **kw)
+    return fde.fde_plan_bytes(p) + 3 * problem.N * 8
+
+
+def run_job(problem, stream=None, keep_state=False, **kw):
+    """One time-stepping job on the current device: assemble, then for every
+    step b = rhs(u), solve M u_new = b from u_new = u.  Returns (infos, u)."""
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device())
+    T = lambda a: None if a is None else torch.as_tensor(a, dtype=torch.float64, device=dev).reshape(-1).contiguous()
+    coef = [T(problem.dplus), T(problem.dminus), T(problem.eplus), T(problem.eminus)]
+    u = T(problem.u0)
+    x = torch.empty_like(u)
+    b = torch.empty_like(u)
+    params = fde.params_for(problem, **kw)
+    handle = fde.fde_assemble(params, *coef, stream=stream)
+    infos = []
+    try:
+        for _ in range(problem.steps):
+            fde.fde_rhs(handle, u, None, b, stream=stream)
+            x.copy_(u)
+            infos.append(fde.fde_solve(handle, b, x, stream=stream))
+            u, x = x, u
+    finally:
+        fde.fde_destroy(handle)
+    return infos, (u if keep_state else None)
+
+
+class Server:
+    """Slots x (stream, worker thread); admission by HBM footprint."""
+
+    def __init__(self, slots: int = 4, hbm_budget: float = 64e9, keep_state: bool = False, **solve_kw):
+        import torch
+        self.slots = slots
+        self.budget = hbm_budget
+        self.keep_state = keep_state
+        self.solve_kw = solve_kw
+        self.streams = [torch.cuda.Stream() for _ in range(slots)]
+        self.cv = threading.Condition()
+        self.pending: list = []       # (arrival time, request) in arrival order
+        self.in_use = 0.0
+        self.closed = False
+        self.results: List[Result] = []
+        self.t0 = None
+        self.threads = [threading.Thread(target=self._worker, args=(i,), daemon=True) for i in range(slots)]
+
+    def start(self):
+        self.t0 = time.perf_counter()
+        for t in self.threads:
+            t.start()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def submit(self, problem, arrival: Optional[float] = None):
+        with self.cv:
+            self.pending.append((self.now() if arrival is None else arrival, problem))
+            self.cv.notify_all()
+
+    def close(self):
+        with self.cv:
+            self.closed = True
+            self.cv.notify_all()
+        for t in self.threads:
+            t.join()
+
+    def _take(self):
+        """Oldest pending request whose footprint fits the free budget."""
+        with self.cv:
+            while True:
+                for i, (arr, prob) in enumerate(self.pending):
+                    need = footprint(prob, **self.solve_kw)
+                    if self.in_use + need <= self.budget or self.in_use == 0.0:
+                        self.pending.pop(i)
+                        self.in_use += need
+                        return arr, prob, need
+                    break   # first come, first served: do not overtake a blocked request
+                if self.closed and not self.pending:
+                    return None
+                self.cv.wait()
+
+    def _release(self, need):
+        with self.cv:
+            self.in_use -= need
+            self.cv.notify_all()
+
+    def _worker(self, slot: int):
+        import torch
+        stream = self.streams[slot]
+        while True:
+            item = self._take()
+            if item is None:
+                return
+            arr, prob, need = item
+            start = self.now()
+            try:
+                with torch.cuda.stream(stream):
+                    infos, u = run_job(prob, stream=stream.cuda_stream, keep_state=self.keep_state,
+                                       **self.solve_kw)
+                    stream.synchronize()
+                res = Result(prob.name, arr, start, self.now(), prob.steps,
+                             [i.iters for i in infos], [i.inner_iters for i in infos],
+                             [i.relres_true for i in infos], u)
+            finally:
+                self._release(need)
+            with self.cv:
+                self.results.append(res)
+
+
+def serve_stream(arrivals, slots: int = 4, hbm_budget: float = 64e9, keep_state: bool = False,
+                 time_scale: float = 1.0, **solve_kw):
+    """Replays a list of fde_inputs.Arrival (Poisson times) against a Server.
+    Returns (results, wall seconds)."""
+    srv = Server(slots=slots, hbm_budget=hbm_budget, keep_state=keep_state, **solve_kw)
+    srv.start()
+    for a in arrivals:
+        delay = a.t * time_scale - srv.now()
+        if delay > 0:
+            time.sleep(delay)
+        srv.submit(a.problem, arrival=a.t * time_scale)
+    srv.close()
+    return srv.results, srv.now()
+
+
+def latency_stats(results) -> dict:
+    import numpy as np
+    lat = np.array([r.latency for r in results])
+    solves = sum(r.steps for r in results)
+    span = max(r.finish for r in results) - min(r.arrival for r in results)
+    return {"requests": len(results), "solves": solves, "p50_ms": float(1e3 * np.percentile(lat, 50)),
+            "p99_ms": float(1e3 * np.percentile(lat, 99)), "mean_ms": float(1e3 * lat.mean()),
+            "solves_per_s": solves / span if span > 0 else 0.0}

@@ -1,0 +1,60 @@
+"""Served (continuous-batching) solves: each request's result is the same
+alone and inside a mix of concurrently running requests, and admission
+respects the HBM budget."""
+import numpy as np
+import pytest
+
+import fde_inputs as fi
+from gpu_util import need_gpu, torch
+
+pytestmark = pytest.mark.gpu
+
+
+def small_stream(rate=2000.0, count=8, seed=21):
+    return fi.served_stream(rate, count, seed=seed, n1d=(255, 4095), n2d=(63, 127, 255), steps=(2, 5))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_alone_equals_mix(precision):
+    fde = need_gpu()
+    from paper_1912_13304_amd import serve
+    arr = small_stream()
+    kw = dict(precision=precision)
+    results, wall = serve.serve_stream(arr, slots=4, keep_state=True, **kw)
+    assert len(results) == len(arr)
+    by_name = {r.name: r for r in results}
+    # requests overlapped on the device: some request started before another finished
+    spans = sorted((r.start, r.finish) for r in results)
+    assert any(spans[i + 1][0] < spans[i][1] for i in range(len(spans) - 1))
+    for a in arr:
+        infos, u = serve.run_job(a.problem, keep_state=True, **kw)
+        torch.cuda.synchronize()
+        r = by_name[a.problem.name]
+        assert r.iters == [i.iters for i in infos]
+        assert torch.equal(r.u, u), a.problem.name   # bitwise: fixed-order reductions
+        assert max(r.relres) <= a.problem.tol * (1 + 1e-6)
+
+
+def test_admission_budget():
+    fde = need_gpu()
+    from paper_1912_13304_amd import serve
+    arr = small_stream(count=6, seed=5)
+    need = [serve.footprint(a.problem) for a in arr]
+    budget = max(need) * 1.2        # at most one large request at a time
+    srv = serve.Server(slots=4, hbm_budget=budget)
+    peak = [0.0]
+    orig = srv._take
+
+    def take():
+        item = orig()
+        peak[0] = max(peak[0], srv.in_use)
+        return item
+    srv._take = take
+    srv.start()
+    for a in arr:
+        srv.submit(a.problem)
+    srv.close()
+    assert len(srv.results) == len(arr)
+    assert peak[0] <= budget
+    st = serve.latency_stats(srv.results)
+    assert st["p99_ms"] >= st["p50_ms"] > 0
