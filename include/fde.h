@@ -23,8 +23,9 @@
  *     invalid.  fde_last_error() returns a thread-local message describing the
  *     last failure.  FDE_ENOTCONV (> 0) means the solver stopped at maxit:
  *     x then holds the last iterate and `info` is filled.
- *   - Transform sizes: every n_i + 1 must be a power of two with
- *     2 <= n_i + 1 <= 4096; other sizes return FDE_EUNSUPPORTED.
+ *   - Transform sizes: every n_i + 1 must be a power of two, with
+ *     2 <= n + 1 <= 2^22 in 1D and 2 <= n_i + 1 <= 4096 in 2D; other sizes
+ *     return FDE_EUNSUPPORTED.
  */
 #ifndef FDE_H
 #define FDE_H

@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "../../include/fde.h"
+#include "fde_bigline.hpp"
 #include "fde_krylov.hpp"
 #include "fde_lines.hpp"
 
@@ -61,6 +62,8 @@ struct Dir {
 
 template <typename T>
 struct Consts {
+  cx<T> *W2p1 = nullptr, *W2p2 = nullptr;                        // four-step factor twiddles (big lines)
+  cx<T>* cw = nullptr;                                           // big-line complex work, 6P
   T *dp = nullptr, *dm = nullptr, *ep = nullptr, *em = nullptr;  // coefficients
   T *ept = nullptr, *emt = nullptr;                              // e+- transposed (n1 x n2)
   T* dinv = nullptr;                                             // D^{-1} (null: no D factor)
@@ -76,6 +79,8 @@ struct fde_plan_s {
   bool has_dinv = false;
   int dside = FDE_D_LEFT;
   Dir rows, trows;   // lines along x (rows of the (n2, n1) array); along y (rows of its transpose)
+  bool big = false;  // 1D line longer than one workgroup: four-step FFT over kernels
+  int P1 = 0, P2 = 0, log1 = 0, log2 = 0;
   Consts<double> c64;
   Consts<float> c32;
   int m = 30, kin = 0;
@@ -157,8 +162,9 @@ static fde_status validate(const fde_params* p) {
       return fail(FDE_EINVAL, "alpha[%d] must lie in (1,2) (got %g)", i, p->alpha[i]);
     if (!(p->hi[i] > p->lo[i]) || !std::isfinite(p->hi[i]) || !std::isfinite(p->lo[i]))
       return fail(FDE_EINVAL, "domain [%g, %g] is empty", p->lo[i], p->hi[i]);
-    if (!is_pow2((long)p->n[i] + 1) || p->n[i] + 1 > 4096)
-      return fail(FDE_EUNSUPPORTED, "n[%d] + 1 = %d must be a power of two <= 4096", i, p->n[i] + 1);
+    const long lim = p->dim == 1 ? (1L << 22) : 4096;
+    if (!is_pow2((long)p->n[i] + 1) || p->n[i] + 1 > lim)
+      return fail(FDE_EUNSUPPORTED, "n[%d] + 1 = %d must be a power of two <= %ld", i, p->n[i] + 1, lim);
   }
   if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(FDE_EINVAL, "dt must be > 0 (got %g)", p->dt);
   if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return fail(FDE_EINVAL, "tol must be > 0 (got %g)", p->tol);
@@ -193,6 +199,7 @@ static size_t plan_bytes_impl(const fde_params* p) {
   else b += (size_t)N * 8 * (2 * m + 1 + 3);
   if (p->precision == FDE_MIXED) b += (size_t)N * 4 * (p->inner_steps + 1 + 6);
   b += (size_t)RED_MAXG * (KMAX + 1) * 8 + 2 * sizeof(KState);
+  if (p->dim == 1 && n1 + 1 > 4096) b += (size_t)(n1 + 1) * (6 * 16 + (p->precision == FDE_MIXED ? 6 * 8 : 0) + 8 * 24);
   return b;
 }
 
@@ -499,6 +506,26 @@ static fde_status assemble_impl(const fde_params* p, const double* dp, const dou
   TRY(upload(pl, &pl->c64.fzero, fz));
   TRY(upload(pl, &pl->c32.fzero, fz));
   TRY(direction_tables(pl, p->alpha[0], n1, &pl->c64.W2x, &pl->c32.W2x, &pl->c64.lamx, &pl->c32.lamx));
+  if (p->dim == 1 && pl->rows.P > 4096) {
+    pl->big = true;
+    const int L = pl->rows.logP;
+    pl->log1 = (L + 1) / 2;
+    pl->log2 = L / 2;
+    pl->P1 = 1 << pl->log1;
+    pl->P2 = 1 << pl->log2;
+    auto sub = [&](int Ps, cx<double>** d, cx<float>** f) -> fde_status {
+      std::vector<std::complex<double>> W(2 * Ps);
+      for (int m = 0; m < 2 * Ps; ++m)
+        W[m] = std::complex<double>(std::cos(M_PI * m / (double)Ps), -std::sin(M_PI * m / (double)Ps));
+      TRY(upload_cx(pl, d, W));
+      TRY(upload_cx(pl, f, W));
+      return FDE_OK;
+    };
+    TRY(sub(pl->P1, &pl->c64.W2p1, &pl->c32.W2p1));
+    TRY(sub(pl->P2, &pl->c64.W2p2, &pl->c32.W2p2));
+    TRY(dalloc(pl, &pl->c64.cw, 6 * (size_t)pl->rows.P));
+    if (p->precision == FDE_MIXED) TRY(dalloc(pl, &pl->c32.cw, 6 * (size_t)pl->rows.P));
+  }
   if (p->dim == 2)
     TRY(direction_tables(pl, p->alpha[1], n2, &pl->c64.W2y, &pl->c32.W2y, &pl->c64.lamy, &pl->c32.lamy));
 
@@ -724,6 +751,95 @@ static void add_y_part(fde_plan pl, const T* x, const T* xpart, T* y, T tscale, 
   transpose<T>(pl, yt, y, pl->n1, pl->n2, xpart, st, skip, skip2);
 }
 
+// ---------------------------------------------------------------------------
+// Big 1D lines (P > 4096)
+// ---------------------------------------------------------------------------
+template <typename T, int LOG>
+static void cfft_rows_k(const cx<T>* in, cx<T>* out, int nrows, const cx<T>* Wsub, const cx<T>* Wbig, int twmod,
+                        int apply, hipStream_t st, const int* skip, const int* skip2) {
+  constexpr int P = 1 << LOG;
+  constexpr int B = P >= 512 ? 1 : 512 / P;
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&cfft_rows_kernel<T, LOG>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_set = true;
+  }
+  const size_t lds = ((size_t)B * (P + 1) + (size_t)B * P) * sizeof(cx<T>);
+  hipLaunchKernelGGL((cfft_rows_kernel<T, LOG>), dim3((nrows + B - 1) / B), dim3(B * P / 8), lds, st, in, out, nrows,
+                     Wsub, Wbig, twmod, apply, skip, skip2);
+}
+
+template <typename T>
+static void cfft_rows(int lg, const cx<T>* in, cx<T>* out, int nrows, const cx<T>* Wsub, const cx<T>* Wbig,
+                      int twmod, int apply, hipStream_t st, const int* skip, const int* skip2) {
+  switch (lg) {
+    case 6: cfft_rows_k<T, 6>(in, out, nrows, Wsub, Wbig, twmod, apply, st, skip, skip2); break;
+    case 7: cfft_rows_k<T, 7>(in, out, nrows, Wsub, Wbig, twmod, apply, st, skip, skip2); break;
+    case 8: cfft_rows_k<T, 8>(in, out, nrows, Wsub, Wbig, twmod, apply, st, skip, skip2); break;
+    case 9: cfft_rows_k<T, 9>(in, out, nrows, Wsub, Wbig, twmod, apply, st, skip, skip2); break;
+    case 10: cfft_rows_k<T, 10>(in, out, nrows, Wsub, Wbig, twmod, apply, st, skip, skip2); break;
+    case 11: cfft_rows_k<T, 11>(in, out, nrows, Wsub, Wbig, twmod, apply, st, skip, skip2); break;
+    default: cfft_rows_k<T, 11>(in, out, nrows, Wsub, Wbig, twmod, apply, st, skip, skip2); break;
+  }
+}
+
+template <typename T>
+static void ctranspose(const cx<T>* in, cx<T>* out, int rows, int cols, int batch, hipStream_t st, const int* skip,
+                       const int* skip2) {
+  const dim3 g((cols + 31) / 32, (rows + 31) / 32, batch);
+  hipLaunchKernelGGL((ctranspose_kernel<T>), g, dim3(256), 0, st, in, out, rows, cols, skip, skip2);
+}
+
+// b = FFT_P(a) for `batch` consecutive lines of P complex values; a is clobbered.
+template <typename T>
+static void big_fft(fde_plan pl, cx<T>* a, cx<T>* b, int batch, hipStream_t st, const int* skip, const int* skip2) {
+  const Consts<T>& c = consts<T>(pl);
+  const int P1 = pl->P1, P2 = pl->P2;
+  ctranspose<T>(a, b, P1, P2, batch, st, skip, skip2);                                     // [j2][j1]
+  cfft_rows<T>(pl->log1, b, a, batch * P2, c.W2p1, c.W2x, P2, 1, st, skip, skip2);         // [j2][k1] * w
+  ctranspose<T>(a, b, P2, P1, batch, st, skip, skip2);                                     // [k1][j2]
+  cfft_rows<T>(pl->log2, b, a, batch * P1, c.W2p2, c.W2x, 1, 0, st, skip, skip2);          // [k1][k2]
+  ctranspose<T>(a, b, P1, P2, batch, st, skip, skip2);                                     // [k2][k1]
+}
+
+static int ew_grid(long N);
+
+// z = S F^{-1} S (pre .* sc v) .* post   (1D big line); z2: optional second copy
+template <typename T>
+static void big_tau(fde_plan pl, const T* v, const double* sc, const T* pre, const T* post, T* z, T* z2,
+                    hipStream_t st, const int* skip, const int* skip2) {
+  const Consts<T>& c = consts<T>(pl);
+  const int P = pl->rows.P, n = pl->n1;
+  cx<T>* c0 = c.cw;
+  cx<T>* c1 = c.cw + P;
+  const int g = ew_grid(P);
+  hipLaunchKernelGGL((pack_dst_kernel<T>), dim3(g), dim3(256), 0, st, v, pre, sc, c0, n, P, skip, skip2);
+  big_fft<T>(pl, c0, c1, 1, st, skip, skip2);
+  hipLaunchKernelGGL((unpack_f_pack_kernel<T>), dim3(g), dim3(256), 0, st, c1, c.W2x, c.fx, c0, P, skip, skip2);
+  big_fft<T>(pl, c0, c1, 1, st, skip, skip2);
+  hipLaunchKernelGGL((unpack_dst_kernel<T>), dim3(g), dim3(256), 0, st, c1, c.W2x, post, z, z2, n, P, skip, skip2);
+}
+
+// out = bscale * base + tscale * (D+ T x + D- T^T x)   (1D big line)
+template <typename T>
+static void big_toep(fde_plan pl, const T* x, const T* base, T bscale, T tscale, T* out, hipStream_t st,
+                     const int* skip, const int* skip2) {
+  const Consts<T>& c = consts<T>(pl);
+  const int P = pl->rows.P, n = pl->n1;
+  cx<T>* c0 = c.cw;
+  cx<T>* c1 = c.cw + P;
+  cx<T>* c2 = c.cw + 2 * P;
+  cx<T>* c3 = c.cw + 4 * P;
+  const int g = ew_grid(P);
+  hipLaunchKernelGGL((pack_toep_kernel<T>), dim3(g), dim3(256), 0, st, x, c0, n, P, skip, skip2);
+  big_fft<T>(pl, c0, c1, 1, st, skip, skip2);
+  hipLaunchKernelGGL((pair_toep_kernel<T>), dim3(g), dim3(256), 0, st, c1, c.lamx, c.W2x, c2, c2 + P, P, skip, skip2);
+  big_fft<T>(pl, c2, c3, 2, st, skip, skip2);
+  hipLaunchKernelGGL((extract_toep_kernel<T>), dim3(g), dim3(256), 0, st, c3, c3 + P, c.dp, c.dm, base, bscale, tscale,
+                     out, n, P, skip, skip2);
+}
+
 // z = P^{-1}(sc * v) (stored when z != null; the DST-side factors D^{-1} as
 // dside says) and w = M z: the fused operator step of the solvers.  With
 // prec NONE, z = sc * v.
@@ -734,6 +850,17 @@ static void tau_matvec(fde_plan pl, const T* v, const double* sc, T* z, T* w, hi
   const bool tau = pl->p.prec != FDE_P_NONE;
   const T* pre = (pl->has_dinv && pl->dside == FDE_D_LEFT) ? c.dinv : nullptr;
   const T* post = (pl->has_dinv && pl->dside == FDE_D_RIGHT) ? c.dinv : nullptr;
+  if (pl->dim == 1 && pl->big) {
+    T* zz = z ? z : pl->tmp<T>(1);
+    if (tau) {
+      big_tau<T>(pl, v, sc, pre, post, zz, nullptr, st, skip, skip2);
+    } else {
+      hipLaunchKernelGGL((scale_cast_kernel<T, T>), dim3(ew_grid(pl->N)), dim3(256), 0, st, v, zz, pl->N, sc, skip,
+                         skip2);
+    }
+    big_toep<T>(pl, zz, zz, (T)pl->nu, T(1), w, st, skip, skip2);
+    return;
+  }
   if (pl->dim == 1) {
     LineArgs<T> a = toep_args<T>(pl, false, skip, skip2);
     a.in = v;
@@ -816,6 +943,10 @@ static void tau_only(fde_plan pl, const T* v, const double* sc, T* z, hipStream_
                        skip, skip2);
     return;
   }
+  if (pl->dim == 1 && pl->big) {
+    big_tau<T>(pl, v, sc, pre, post, z, nullptr, st, skip, skip2);
+    return;
+  }
   if (pl->dim == 1) {
     LineArgs<T> a{};
     a.in = v;
@@ -867,6 +998,10 @@ static void tau_only(fde_plan pl, const T* v, const double* sc, T* z, hipStream_
 template <typename T>
 static void matvec_only(fde_plan pl, const T* x, T* y, T bscale, T tscale, hipStream_t st, const int* skip,
                         const int* skip2 = nullptr) {
+  if (pl->dim == 1 && pl->big) {
+    big_toep<T>(pl, x, x, bscale, tscale, y, st, skip, skip2);
+    return;
+  }
   LineArgs<T> a = toep_args<T>(pl, false, skip, skip2);
   a.in = x;
   a.bscale = bscale;

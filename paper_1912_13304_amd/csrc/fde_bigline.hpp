@@ -1,0 +1,230 @@
+// Transforms of one 1D line longer than a workgroup holds (P = n + 1 > 4096).
+//
+// The complex P-point FFT is a four-step FFT over kernels, P = P1 * P2 with
+// both factors <= 4096: view x (j = j1 P2 + j2) as a P1 x P2 array,
+// transpose, FFT the P2 rows of length P1 and multiply entry (j2, k1) by
+// exp(-2 pi i j2 k1 / P), transpose, FFT the P1 rows of length P2, transpose:
+// X[k1 + P1 k2] lands at position k2 P1 + k1, the natural order.
+//
+// The DST-I and Toeplitz programs use the same packings as the one-workgroup
+// line kernels (odd extension / zero padding packed into P complex points,
+// bins k and P - k paired), here as elementwise kernels around the big FFT;
+// the division by the symbol between the two DSTs of the preconditioner is
+// fused with the unpacking of the first and the packing of the second.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fde_krylov.hpp"
+#include "fde_lines.hpp"
+
+namespace fde {
+
+__device__ __forceinline__ bool skip2f(const int* a, const int* b) { return (a && *a) || (b && *b); }
+
+// Rows of length P = 2^LOGP (row-major complex array of nrows rows): FFT of
+// every row; with apply_tw, entry (r, k) is then multiplied by
+// exp(-2 pi i (r mod twmod) k / Pbig) = Wbig[2 ((r mod twmod) k)], where Wbig
+// is the table exp(-i pi m / Pbig), m < 2 Pbig.
+template <typename T, int LOGP>
+__global__ void __launch_bounds__(512)
+cfft_rows_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int nrows, const cx<T>* __restrict__ Wsub,
+                 const cx<T>* __restrict__ Wbig, int twmod, int apply_tw, const int* skip, const int* skip2) {
+  constexpr int EPT = 8;
+  constexpr int P = 1 << LOGP;
+  constexpr int B = P >= 512 ? 1 : 512 / P;
+  constexpr int NTH = B * P / EPT;
+  constexpr int LS = P + 1;
+  if (skip2f(skip, skip2)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* tw = buf + B * LS;
+  const int tid = threadIdx.x;
+  const int row0 = blockIdx.x * B;
+  cx<T> v[EPT];
+  T twr[8], twi[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const cx<T> t = Wsub[(tid + k * NTH) & (P - 1)];
+    twr[k] = t.x;
+    twi[k] = t.y;
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = tid + i * NTH;
+    const int l = e >> LOGP, m = e & (P - 1);
+    const int r = min(row0 + l, nrows - 1);
+    v[i] = in[(long)r * P + m];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) tw[tid + k * NTH] = mk(twr[k], twi[k]);
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = tid + i * NTH;
+    buf[(e >> LOGP) * LS + (e & (P - 1))] = v[i];
+  }
+  __syncthreads();
+  fft_lines_ct<T, EPT, LOGP, 0>(buf, LS, tw);
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = tid + i * NTH;
+    const int l = e >> LOGP, k = e & (P - 1);
+    const int r = row0 + l;
+    if (r < nrows) {
+      cx<T> x = buf[l * LS + k];
+      if (apply_tw) x = mul(x, Wbig[2 * ((r % twmod) * k)]);
+      out[(long)r * P + k] = x;
+    }
+  }
+}
+
+// DST packing: z_j = u_{2j} + i u_{2j+1}, u the odd extension (length 2P) of
+// x_m = sc * pre_m * in_{m-1}, m = 1..n (u_0 = u_P = 0, u_{2P-m} = -x_m).
+template <typename T>
+__global__ void pack_dst_kernel(const T* in, const T* pre, const double* sc, cx<T>* z, int n, int P,
+                                const int* skip, const int* skip2) {
+  if (skip2f(skip, skip2)) return;
+  const T s = sc ? (T)(*sc) : T(1);
+  auto u = [&](int m) -> T {
+    if (m == 0 || m == P) return T(0);
+    const int mm = m < P ? m : 2 * P - m;
+    T x = in[mm - 1] * s;
+    if (pre) x *= pre[mm - 1];
+    return m < P ? x : -x;
+  };
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < P; j += gridDim.x * blockDim.x) z[j] = mk(u(2 * j), u(2 * j + 1));
+}
+
+// DST value y_k (k = 1..n) from the P-point FFT Z of the packed odd extension.
+template <typename T>
+__device__ __forceinline__ T dst_value(const cx<T>* Z, const cx<T>* W, int k, int P) {
+  const cx<T> zk = Z[k], zn = Z[P - k], w = W[k];
+  const T imU = T(0.5) * ((zk.y - zn.y) - w.x * (zk.x - zn.x) + w.y * (zk.y + zn.y));
+  return -imU / sqrt(T(2 * P));
+}
+
+// y_{m+1} -> out[m] (times post_m when post), m < n.
+template <typename T>
+__global__ void unpack_dst_kernel(const cx<T>* Z, const cx<T>* W, const T* post, T* out, T* out2, int n, int P,
+                                  const int* skip, const int* skip2) {
+  if (skip2f(skip, skip2)) return;
+  for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < n; m += gridDim.x * blockDim.x) {
+    T y = dst_value(Z, W, m + 1, P);
+    if (post) y *= post[m];
+    out[m] = y;
+    if (out2) out2[m] = y;
+  }
+}
+
+// Between the two DSTs of the preconditioner: y = DST(x) from Z, divide by F
+// (F_m = f[m - 1]), and pack the odd extension of y / F for the second DST.
+template <typename T>
+__global__ void unpack_f_pack_kernel(const cx<T>* Z, const cx<T>* W, const T* f, cx<T>* z2, int P,
+                                     const int* skip, const int* skip2) {
+  if (skip2f(skip, skip2)) return;
+  auto u = [&](int m) -> T {
+    if (m == 0 || m == P) return T(0);
+    const int mm = m < P ? m : 2 * P - m;
+    const T y = dst_value(Z, W, mm, P) / f[mm - 1];
+    return m < P ? y : -y;
+  };
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < P; j += gridDim.x * blockDim.x) z2[j] = mk(u(2 * j), u(2 * j + 1));
+}
+
+// Toeplitz packing: q_j = p_{2j} + i p_{2j+1}, p = (z_0..z_{n-1}, 0, ..., 0) of length 2P.
+template <typename T>
+__global__ void pack_toep_kernel(const T* zin, cx<T>* q, int n, int P, const int* skip, const int* skip2) {
+  if (skip2f(skip, skip2)) return;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < P; j += gridDim.x * blockDim.x) {
+    const int a = 2 * j, b = 2 * j + 1;
+    q[j] = mk(a < n ? zin[a] : T(0), b < n ? zin[b] : T(0));
+  }
+}
+
+// Pair phase of the Toeplitz product: from Q (FFT of the packed zero-padded
+// input) form the half spectrum Ph, Y1 = lam Ph, Y2 = conj(lam) Ph, and the
+// conjugated packed inverse inputs conj(W1), conj(W2) at bins k and P - k.
+template <typename T>
+__global__ void pair_toep_kernel(const cx<T>* Q, const cx<T>* lam, const cx<T>* W, cx<T>* W1, cx<T>* W2, int P,
+                                 const int* skip, const int* skip2) {
+  if (skip2f(skip, skip2)) return;
+  const int H = P / 2;
+  auto winv = [&](cx<T> yk, cx<T> yn, cx<T> w) -> cx<T> {
+    const cx<T> s = scale(add(yk, conj(yn)), T(0.5));
+    const cx<T> d = scale(sub(yk, conj(yn)), T(0.5));
+    return add(s, mul_i(mul(conj(w), d)));
+  };
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k <= H; k += gridDim.x * blockDim.x) {
+    if (k == 0) {
+      const cx<T> q0 = Q[0];
+      const T p0 = q0.x + q0.y, pP = q0.x - q0.y;
+      const cx<T> l0 = lam[0], lP = lam[P], one = mk(T(1), T(0));
+      W1[0] = conj(winv(scale(l0, p0), scale(lP, pP), one));
+      W2[0] = conj(winv(scale(conj(l0), p0), scale(conj(lP), pP), one));
+    } else if (k == H) {
+      const cx<T> ph = conj(Q[H]);
+      const cx<T> w = mk(T(0), T(-1));
+      const cx<T> y1 = mul(lam[H], ph), y2 = mul(conj(lam[H]), ph);
+      W1[H] = conj(winv(y1, y1, w));
+      W2[H] = conj(winv(y2, y2, w));
+    } else {
+      const cx<T> qk = Q[k], qn = Q[P - k];
+      const cx<T> E = scale(add(qk, conj(qn)), T(0.5));
+      const cx<T> O = mul_mi(scale(sub(qk, conj(qn)), T(0.5)));
+      const cx<T> w = W[k];
+      const cx<T> wO = mul(w, O);
+      const cx<T> pk = add(E, wO), pn = conj(sub(E, wO));
+      const cx<T> lk = lam[k], ln = lam[P - k];
+      const cx<T> wn = mk(-w.x, w.y);
+      W1[k] = conj(winv(mul(lk, pk), mul(ln, pn), w));
+      W1[P - k] = conj(winv(mul(ln, pn), mul(lk, pk), wn));
+      W2[k] = conj(winv(mul(conj(lk), pk), mul(conj(ln), pn), w));
+      W2[P - k] = conj(winv(mul(conj(ln), pn), mul(conj(lk), pk), wn));
+    }
+  }
+}
+
+// out_m = bscale * base_m + tscale * (cplus_m y1_m + cminus_m y2_m), where
+// y_{2j} = Re R_j / P and y_{2j+1} = -Im R_j / P for R = FFT(conj W).
+template <typename T>
+__global__ void extract_toep_kernel(const cx<T>* R1, const cx<T>* R2, const T* cplus, const T* cminus,
+                                    const T* base, T bscale, T tscale, T* out, int n, int P, const int* skip,
+                                    const int* skip2) {
+  if (skip2f(skip, skip2)) return;
+  const T invP = T(1) / T(P);
+  for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < n; m += gridDim.x * blockDim.x) {
+    const cx<T> r1 = R1[m >> 1], r2 = R2[m >> 1];
+    const T y1 = ((m & 1) ? -r1.y : r1.x) * invP;
+    const T y2 = ((m & 1) ? -r2.y : r2.x) * invP;
+    out[m] = bscale * base[m] + tscale * (cplus[m] * y1 + cminus[m] * y2);
+  }
+}
+
+// Batched complex transpose: for each z < batch, out_z (cols x rows) = in_z^T.
+template <typename T>
+__global__ void __launch_bounds__(256)
+ctranspose_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int rows, int cols, const int* skip,
+                  const int* skip2) {
+  if (skip2f(skip, skip2)) return;
+  __shared__ cx<T> tile[32][33];
+  const long zoff = (long)blockIdx.z * rows * cols;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  cx<T> t[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = min(r0 + ty + 8 * i, rows - 1), c = min(c0 + tx, cols - 1);
+    t[i] = in[zoff + (long)r * cols + c];
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) tile[ty + 8 * i][tx] = t[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int c = c0 + ty + 8 * i, r = r0 + tx;
+    if (c < cols && r < rows) out[zoff + (long)c * rows + r] = tile[tx][ty + 8 * i];
+  }
+}
+
+}  // namespace fde
