@@ -171,6 +171,77 @@ enum { FDE_PROBE_OFF = 0,
 fde_status fde_probe(fde_plan plan, int cls);
 fde_status fde_probe_read(fde_plan plan, double* ms, long long* launches, double* bytes);
 
+/* ---------------------------------------------------------------------------
+ * Batched 1D solves: many independent systems M_i u_i = b_i (Section 1.2,
+ * eq. linsystem), each with its own n_i, alpha_i, coefficients and
+ * parameters, solved together in one persistent launch.  Each instance is
+ * solved by one workgroup with the right-preconditioned FGMRES of fde_solve
+ * (float64, or the mixed form), so its result does not depend on the rest of
+ * the batch.  Any n_i in 1..65535 is accepted: when n_i + 1 is not a power
+ * of two the DST-I is evaluated by the chirp-z identity with power-of-two
+ * FFTs.
+ *
+ * Packing: batch vectors are the instances' vectors concatenated in order;
+ * instance i occupies elements [off_i, off_i + n_i) with
+ * off_i = n_0 + ... + n_{i-1} (fde_batch_layout returns the offsets).
+ * Restrictions: dim = 1, solver = FDE_S_GMRES, restart <= 32.
+ * ------------------------------------------------------------------------- */
+typedef struct fde_batch_s* fde_batch;
+
+/* Launch configurations: variant selects the workgroup size and FFT radix
+   (0: 512 threads, radix 8; 1: 512 threads, radix 4; 2 and 3, the
+   256-thread forms, are disabled and rejected with FDE_EUNSUPPORTED); grid
+   is the number of persistent workgroups; lpt = 1 hands out instances
+   longest-estimated-work first, 0 in the given order.  ms: the time of one
+   step measured by the tuner. */
+enum { FDE_BATCH_VARIANTS = 4 };
+typedef struct {
+  int    variant;
+  int    grid;
+  int    lpt;
+  double ms;
+} fde_batch_cfg;
+
+/* Offsets of the packed layout (offsets: host array of count + 1 entries, or
+   NULL); returns the total length, 0 when a parameter set is invalid. */
+size_t fde_batch_layout(const fde_params* params, int count, long long* offsets);
+
+/* Device bytes a batch with these parameters allocates. */
+size_t fde_batch_bytes(const fde_params* params, int count);
+
+/* Builds a batch from count parameter sets (host array) and the packed
+   device arrays d+ and d- (length fde_batch_layout(...)).  Validation as in
+   fde_assemble, per instance; FDE_EUNSUPPORTED for dim != 1, PCG or n > 65535.
+   Synchronises `stream`. */
+fde_status fde_batch_assemble(const fde_params* params, int count, const double* dplus,
+                              const double* dminus, void* stream, fde_batch* out);
+
+/* Solves every instance: b packed right-hand sides, x packed start vectors
+   on entry and solutions on return (device).  info: host array of count
+   entries or NULL.  FDE_ENOTCONV / FDE_ENONFINITE when any instance did not
+   converge / met a non-finite value (the others are still solved).
+   Synchronises `stream`. */
+fde_status fde_batch_solve(fde_batch batch, const double* b, double* x, fde_info* info, void* stream);
+
+/* Time stepping: `steps` implicit steps of every instance from the packed
+   state u (device, advanced in place): b = rhs(u) with f = 0 (fde_rhs), then
+   M u_new = b solved from u_new = u.  With use_graph != 0 one step (queue
+   reset, solve launch, step counter) is captured once as a HIP graph and
+   replayed per step.  info: host array of steps * count entries (step-major)
+   or NULL.  Synchronises `stream`. */
+fde_status fde_batch_run(fde_batch batch, double* u, int steps, int use_graph, fde_info* info,
+                         void* stream);
+
+/* Autotuner: times one time step from the packed state u (not modified) for
+   every launch configuration and keeps the fastest; `chosen` (may be NULL)
+   receives it.  Synchronises `stream`. */
+fde_status fde_batch_tune(fde_batch batch, const double* u, void* stream, fde_batch_cfg* chosen);
+fde_status fde_batch_get_cfg(fde_batch batch, fde_batch_cfg* cfg);
+fde_status fde_batch_set_cfg(fde_batch batch, const fde_batch_cfg* cfg);
+
+/* Releases the batch (synchronises the device first). NULL is ignored. */
+void fde_batch_destroy(fde_batch batch);
+
 /* Thread-local description of the last error, "" when none. */
 const char* fde_last_error(void);
 

@@ -32,7 +32,10 @@ LINE_PROGRAMS = {1: "dst", 3: "dst_f_dst", 8: "toeplitz", 11: "dst_f_dst_toeplit
                  13: "dst_storez_toeplitz", 15: "dst_f_dst_storez_toeplitz"}
 
 EXPORTED = ["fde_default_params", "fde_assemble", "fde_matvec", "fde_tau_apply", "fde_solve", "fde_rhs",
-            "fde_plan_bytes", "fde_destroy", "fde_last_error", "fde_probe", "fde_probe_read"]
+            "fde_plan_bytes", "fde_destroy", "fde_last_error", "fde_probe", "fde_probe_read",
+            "fde_batch_layout", "fde_batch_bytes", "fde_batch_assemble", "fde_batch_solve", "fde_batch_run",
+            "fde_batch_tune", "fde_batch_get_cfg", "fde_batch_set_cfg", "fde_batch_destroy"]
+BATCH_VARIANTS = 4
 
 
 class FdeParams(ctypes.Structure):
@@ -67,6 +70,13 @@ class FdeInfo(ctypes.Structure):
         ("relres_est", ctypes.c_double),
         ("seconds", ctypes.c_double),
     ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class FdeBatchCfg(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int), ("grid", ctypes.c_int), ("lpt", ctypes.c_int), ("ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -111,6 +121,25 @@ def load(path: str = LIB_PATH):
     lib.fde_probe_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong),
                                    ctypes.POINTER(ctypes.c_double)]
     lib.fde_probe_read.restype = ctypes.c_int
+    cp = ctypes.POINTER(FdeBatchCfg)
+    lib.fde_batch_layout.argtypes = [dp, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong)]
+    lib.fde_batch_layout.restype = ctypes.c_size_t
+    lib.fde_batch_bytes.argtypes = [dp, ctypes.c_int]
+    lib.fde_batch_bytes.restype = ctypes.c_size_t
+    lib.fde_batch_assemble.argtypes = [dp, ctypes.c_int, vp, vp, vp, ctypes.POINTER(vp)]
+    lib.fde_batch_assemble.restype = ctypes.c_int
+    lib.fde_batch_solve.argtypes = [vp, vp, vp, ctypes.POINTER(FdeInfo), vp]
+    lib.fde_batch_solve.restype = ctypes.c_int
+    lib.fde_batch_run.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(FdeInfo), vp]
+    lib.fde_batch_run.restype = ctypes.c_int
+    lib.fde_batch_tune.argtypes = [vp, vp, vp, cp]
+    lib.fde_batch_tune.restype = ctypes.c_int
+    lib.fde_batch_get_cfg.argtypes = [vp, cp]
+    lib.fde_batch_get_cfg.restype = ctypes.c_int
+    lib.fde_batch_set_cfg.argtypes = [vp, cp]
+    lib.fde_batch_set_cfg.restype = ctypes.c_int
+    lib.fde_batch_destroy.argtypes = [vp]
+    lib.fde_batch_destroy.restype = None
     lib.fde_last_error.argtypes = []
     lib.fde_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -248,6 +277,106 @@ class Plan:
     def close(self):
         if self.handle:
             fde_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+# ---------------------------------------------------------------------------
+# Batched 1D solves (fde_batch_*)
+# ---------------------------------------------------------------------------
+def _params_array(params):
+    arr = (FdeParams * len(params))()
+    for i, p in enumerate(params):
+        arr[i] = p
+    return arr
+
+
+def fde_batch_layout(params):
+    """(offsets of the packed layout (count + 1 entries), total length)."""
+    arr = _params_array(params)
+    off = (ctypes.c_longlong * (len(params) + 1))()
+    total = load().fde_batch_layout(arr, len(params), off)
+    if total == 0:
+        raise FdeError(FDE_EINVAL, fde_last_error())
+    return list(off), int(total)
+
+
+def fde_batch_bytes(params) -> int:
+    arr = _params_array(params)
+    return int(load().fde_batch_bytes(arr, len(params)))
+
+
+class Batch:
+    """Owns an fde_batch: many 1D instances (fde_inputs.Problem each) solved
+    together.  Packed vectors are float64 CUDA tensors of length ``total``."""
+
+    def __init__(self, problems, device="cuda", stream=None, **kw):
+        import torch
+        self.problems = list(problems)
+        self.params = [params_for(p, **kw) for p in self.problems]
+        self.offsets, self.total = fde_batch_layout(self.params)
+        cat = lambda key: torch.as_tensor(
+            [v for p in self.problems for v in list(getattr(p, key))], dtype=torch.float64, device=device)
+        dp, dm = cat("dplus"), cat("dminus")
+        arr = _params_array(self.params)
+        h = ctypes.c_void_p()
+        _check(load().fde_batch_assemble(arr, len(self.params), _ptr(dp), _ptr(dm), _stream(stream),
+                                         ctypes.byref(h)))
+        self.handle = h
+        self.count = len(self.params)
+
+    def pack(self, arrays, device="cuda"):
+        import numpy as np
+        import torch
+        return torch.as_tensor(np.concatenate([np.asarray(a, dtype=np.float64).reshape(-1) for a in arrays]),
+                               dtype=torch.float64, device=device)
+
+    def unpack(self, t):
+        h = t.detach().cpu().numpy()
+        return [h[self.offsets[i]:self.offsets[i + 1]] for i in range(self.count)]
+
+    def solve(self, b, x, stream=None, allow_notconv=False):
+        infos = (FdeInfo * self.count)()
+        st = load().fde_batch_solve(self.handle, _ptr(b), _ptr(x), infos, _stream(stream))
+        _check(st, allow_notconv)
+        return list(infos)
+
+    def run(self, u, steps, use_graph=True, stream=None, allow_notconv=False):
+        """Advances the packed state u by `steps` implicit steps; returns
+        infos[step][instance]."""
+        infos = (FdeInfo * (steps * self.count))()
+        st = load().fde_batch_run(self.handle, _ptr(u), int(steps), int(bool(use_graph)), infos, _stream(stream))
+        _check(st, allow_notconv)
+        return [list(infos[s * self.count:(s + 1) * self.count]) for s in range(steps)]
+
+    def tune(self, u, stream=None) -> FdeBatchCfg:
+        c = FdeBatchCfg()
+        _check(load().fde_batch_tune(self.handle, _ptr(u), _stream(stream), ctypes.byref(c)))
+        return c
+
+    def get_cfg(self) -> FdeBatchCfg:
+        c = FdeBatchCfg()
+        _check(load().fde_batch_get_cfg(self.handle, ctypes.byref(c)))
+        return c
+
+    def set_cfg(self, variant, grid, lpt=1):
+        c = FdeBatchCfg(int(variant), int(grid), int(lpt), 0.0)
+        _check(load().fde_batch_set_cfg(self.handle, ctypes.byref(c)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().fde_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

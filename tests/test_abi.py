@@ -76,3 +76,58 @@ def test_plan_bytes_grows_with_size(fde):
     c = fde.fde_plan_bytes(p)
     assert 0 < a < b < c
     assert b > 62 * 1023 * 1023 * 8   # 2m+1 basis vectors of N float64
+
+
+def batch_params(fde, sizes):
+    ps = []
+    for n in sizes:
+        p = fde.fde_default_params()
+        p.n[0] = n
+        p.dt = 2.0 / (n + 1)
+        ps.append(p)
+    return ps
+
+
+def test_batch_layout_and_bytes(fde):
+    ps = batch_params(fde, [255, 1000, 3, 16383])
+    off, total = fde.fde_batch_layout(ps)
+    assert off == [0, 255, 1255, 1258, 17641] and total == 17641
+    b1 = fde.fde_batch_bytes(ps)
+    b2 = fde.fde_batch_bytes(ps + batch_params(fde, [16383]))
+    assert b2 > b1 > 31 * 17641 * 8   # at least the float64 Krylov bases
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("dim", 2, -1), ("solver", 1, -5), ("n", (65536, 1), -5), ("n", (0, 1), -1), ("restart", 33, -1),
+    ("alpha", (1.0, 1.5), -1), ("inner_steps", 40, -1),
+])
+def test_batch_invalid_parameters(fde, field, value, status):
+    ps = batch_params(fde, [100, 200])
+    p = ps[1]
+    if field == "inner_steps":
+        p.precision = fde.MIXED
+    if isinstance(value, tuple):
+        for i, v in enumerate(value):
+            getattr(p, field)[i] = v
+    else:
+        setattr(p, field, value)
+    arr = fde._params_array(ps)
+    h = ctypes.c_void_p()
+    st = fde.load().fde_batch_assemble(arr, 2, None, None, None, ctypes.byref(h))
+    assert st == status
+    assert not h.value
+    assert "instance 1" in fde.fde_last_error()
+    assert fde.load().fde_batch_layout(arr, 2, None) == 0
+    assert fde.fde_batch_bytes(ps) == 0
+
+
+def test_batch_count_rejected(fde):
+    arr = fde._params_array(batch_params(fde, [10]))
+    h = ctypes.c_void_p()
+    assert fde.load().fde_batch_assemble(arr, 0, None, None, None, ctypes.byref(h)) == -1
+
+
+def test_batch_disabled_variants_rejected(fde):
+    # set_cfg validates before touching the batch's device state; a NULL batch is rejected first
+    c = fde.FdeBatchCfg(2, 8, 1, 0.0)
+    assert fde.load().fde_batch_set_cfg(None, ctypes.byref(c)) == -1

@@ -1,0 +1,234 @@
+"""Batched 1D solves (one persistent launch for many uneven instances):
+parity of every instance with the oracle's build-mode FGMRES, the chirp-z
+DST for sizes where n + 1 is not a power of two, the staged FFT for long
+lines, the mixed form, time stepping through the captured graph, and the
+independence of an instance's result from the rest of the batch."""
+import numpy as np
+import pytest
+
+import fde_inputs as fi
+from gpu_util import dev, host, need_gpu, relerr, torch
+from oracle import krylov, precond as pc
+from oracle.system import FDESystem
+
+pytestmark = pytest.mark.gpu
+
+
+def inst(n, alpha, seed, weights="shifted", time="euler", fac=1.0):
+    p = fi.variable_1d(n=n, alpha=alpha, seed=seed, steps=1)
+    p.weights, p.time = weights, time
+    p.dplus = p.dplus * fac
+    p.dminus = p.dminus * fac
+    return p
+
+
+def oracle_solve(p, prec="tau", dside="left", restart=30, tol=1e-8):
+    s = FDESystem.from_problem(p)
+    b = s.rhs(p.u0)
+    P = pc.make(prec, s, dside=dside)
+    x, info = krylov.fgmres(s.matvec, b, P, x0=p.u0, restart=restart, tol=tol)
+    return s, b, x, info
+
+
+def check_fp64(p, xg, ig, prec="tau", dside="left", restart=30, tol=1e-8):
+    s, b, xo, io = oracle_solve(p, prec, dside, restart, tol)
+    assert ig.converged and io["converged"], (p.name, ig.as_dict())
+    assert abs(ig.iters - io["iters"]) <= 1, (p.n, ig.iters, io["iters"])
+    assert relerr(s.matvec(xg), b) <= tol * (1 + 1e-6)
+    if ig.iters == io["iters"]:
+        assert relerr(xg, xo) < 1e-10, (p.n, relerr(xg, xo))
+
+
+# sizes: tiny, n + 1 a power of two (direct DST), arbitrary n (chirp-z DST),
+# Toeplitz and DST both in LDS, and long enough for the staged FFT
+SIZES_SMALL = [1, 2, 3, 5, 7, 8, 15, 100, 255, 256, 1000, 1023]
+SIZES_LARGE = [2047, 3000, 4095, 5000, 8191, 12345]
+
+
+def batch_solve(problems, fde, **kw):
+    with fde.Batch(problems, **kw) as bt:
+        b = bt.pack([FDESystem.from_problem(p).rhs(p.u0) for p in problems])
+        x = bt.pack([p.u0 for p in problems])
+        infos = bt.solve(b, x)
+        return bt.unpack(x), infos
+
+
+def test_batch_small_fp64():
+    fde = need_gpu()
+    probs = [inst(n, 1.1 + 0.8 * ((7 * i) % 11) / 10.0, 100 + i) for i, n in enumerate(SIZES_SMALL)]
+    xs, infos = batch_solve(probs, fde)
+    for p, xg, ig in zip(probs, xs, infos):
+        check_fp64(p, xg, ig)
+
+
+def test_batch_large_fp64():
+    fde = need_gpu()
+    probs = [inst(n, 1.25 + 0.1 * i, 200 + i) for i, n in enumerate(SIZES_LARGE)]
+    xs, infos = batch_solve(probs, fde)
+    for p, xg, ig in zip(probs, xs, infos):
+        check_fp64(p, xg, ig)
+
+
+@pytest.mark.parametrize("weights,time", [("weighted", "cn"), ("shifted", "cn"), ("weighted", "euler")])
+@pytest.mark.parametrize("dside", ["left", "right"])
+def test_batch_schemes(weights, time, dside):
+    fde = need_gpu()
+    probs = [inst(n, a, 300 + n, weights, time) for n, a in [(63, 1.3), (200, 1.7), (1023, 1.5), (1500, 1.2)]]
+    xs, infos = batch_solve(probs, fde, dside=fde.D_LEFT if dside == "left" else fde.D_RIGHT)
+    for p, xg, ig in zip(probs, xs, infos):
+        check_fp64(p, xg, ig, dside=dside)
+
+
+@pytest.mark.parametrize("prec", ["none", "tilde", "tau_hat"])
+def test_batch_preconditioners(prec):
+    fde = need_gpu()
+    code = {"none": fde.P_NONE, "tilde": fde.P_TILDE, "tau_hat": fde.P_TAU_HAT}[prec]
+    probs = []
+    for i, n in enumerate([15, 31, 63] if prec == "none" else [31, 100, 511]):
+        p = inst(n, 1.3 + 0.2 * i, 400 + i)
+        if prec == "tau_hat":
+            p.dplus = np.full(n, 1.5)
+            p.dminus = np.full(n, 1.5)
+        probs.append(p)
+    xs, infos = batch_solve(probs, fde, prec=code, maxit=20000)
+    for p, xg, ig in zip(probs, xs, infos):
+        s, b, xo, io = oracle_solve(p, prec)
+        assert ig.converged and io["converged"]
+        # long unpreconditioned runs may drift by a few restarts' worth of rounding
+        assert abs(ig.iters - io["iters"]) <= max(1, 0.005 * io["iters"]), (p.n, ig.iters, io["iters"])
+        assert relerr(s.matvec(xg), b) <= 1e-8 * (1 + 1e-6)
+        if ig.iters == io["iters"]:
+            assert relerr(xg, xo) < 1e-10
+
+
+@pytest.mark.parametrize("variant", [
+    0, 1,
+    pytest.param(2, marks=pytest.mark.skip(reason="256-thread variant disabled: it took a GPU memory fault "
+                                                  "whose cause was not found (the CPU emulation runs clean)")),
+    pytest.param(3, marks=pytest.mark.skip(reason="256-thread variant disabled with variant 2")),
+])
+def test_batch_variants(variant):
+    """Every enabled launch configuration (workgroup size x FFT radix) solves alike."""
+    fde = need_gpu()
+    probs = [inst(n, a, 500 + n) for n, a in [(127, 1.4), (999, 1.6), (4095, 1.8), (6000, 1.5)]]
+    with fde.Batch(probs) as bt:
+        bt.set_cfg(variant, 7, lpt=(variant + 1) % 2)
+        b = bt.pack([FDESystem.from_problem(p).rhs(p.u0) for p in probs])
+        x = bt.pack([p.u0 for p in probs])
+        infos = bt.solve(b, x)
+        xs = bt.unpack(x)
+    for p, xg, ig in zip(probs, xs, infos):
+        check_fp64(p, xg, ig)
+
+
+def test_batch_mixed():
+    fde = need_gpu()
+    probs = [inst(n, a, 600 + n) for n, a in [(255, 1.3), (1000, 1.5), (4095, 1.7), (7000, 1.2)]]
+    for inner in (0, 16):
+        xs, infos = batch_solve(probs, fde, precision=fde.MIXED, inner_steps=inner)
+        for p, xg, ig in zip(probs, xs, infos):
+            s, b, xo, io = oracle_solve(p)
+            assert ig.converged
+            assert relerr(s.matvec(xg), b) <= 1e-8 * (1 + 1e-6)   # float64 true residual, by the oracle
+            assert relerr(xg, xo) < 1e-6
+
+
+def test_batch_alone_equals_mix():
+    """An instance's iterates do not depend on the other instances."""
+    fde = need_gpu()
+    probs = [inst(n, a, 700 + n) for n, a in [(300, 1.4), (2047, 1.6), (5000, 1.3), (77, 1.9)]]
+    xs, infos = batch_solve(probs, fde)
+    for k in (0, 2):
+        xa, ia = batch_solve([probs[k]], fde)
+        assert ia[0].iters == infos[k].iters
+        assert np.array_equal(xa[0], xs[k])
+
+
+def test_batch_run_graph_matches_eager():
+    """Time stepping: the replayed graph gives bit-identical states and
+    iteration counts to eager launches, step by step."""
+    fde = need_gpu()
+    probs = [inst(n, a, 800 + n) for n, a in [(255, 1.5), (1000, 1.3), (3000, 1.7)]]
+    steps = 3
+    with fde.Batch(probs) as bt:
+        u0 = bt.pack([p.u0 for p in probs])
+        ug = u0.clone()
+        ue = u0.clone()
+        ig = bt.run(ug, steps, use_graph=True)
+        ie = bt.run(ue, steps, use_graph=False)
+        assert torch.equal(ug, ue)
+        for s in range(steps):
+            assert [i.iters for i in ig[s]] == [i.iters for i in ie[s]]
+        # a second graph run continues from the state (graph replayed again)
+        ug2 = ug.clone()
+        bt.run(ug2, 1, use_graph=True)
+        ue2 = ue.clone()
+        bt.run(ue2, 1, use_graph=False)
+        assert torch.equal(ug2, ue2)
+        xs = bt.unpack(ug)
+    # the state after `steps` implicit steps, by the oracle (same solver, x0 = u)
+    for p, xg in zip(probs, xs):
+        s = FDESystem.from_problem(p)
+        u = p.u0.copy()
+        for _ in range(steps):
+            u, io = krylov.fgmres(s.matvec, s.rhs(u), pc.make("tau", s), x0=u, restart=30, tol=1e-8)
+        assert relerr(xg, u) < 1e-7
+
+
+def test_batch_edge_cases():
+    fde = need_gpu()
+    probs = [inst(n, 1.5, 900 + n) for n in (10, 20, 30)]
+    with fde.Batch(probs) as bt:
+        bvals = [FDESystem.from_problem(p).rhs(p.u0) for p in probs]
+        bvals[1] = np.zeros(20)
+        b = bt.pack(bvals)
+        x = bt.pack([p.u0 for p in probs])
+        infos = bt.solve(b, x)
+        xs = bt.unpack(x)
+        assert infos[1].converged and infos[1].iters == 0 and np.all(xs[1] == 0.0)
+        check_fp64(probs[0], xs[0], infos[0])
+        # a non-finite right-hand side is reported, the other instances are still solved
+        bvals[2] = bvals[2].copy()
+        bvals[2][3] = np.nan
+        b = bt.pack(bvals)
+        x = bt.pack([p.u0 for p in probs])
+        with pytest.raises(fde.FdeError) as e:
+            bt.solve(b, x)
+        assert e.value.status == fde.FDE_ENONFINITE
+    # maxit reached: FDE_ENOTCONV with the last iterate
+    with fde.Batch(probs[:1], maxit=2) as bt:
+        b = bt.pack([FDESystem.from_problem(probs[0]).rhs(probs[0].u0)])
+        x = bt.pack([probs[0].u0])
+        infos = bt.solve(b, x, allow_notconv=True)
+        assert infos[0].iters == 2 and not infos[0].converged
+
+
+def test_batch_tune():
+    fde = need_gpu()
+    probs = fi.batched_1d(count=24, seed=4, nmax=4095, steps=1)
+    with fde.Batch(probs) as bt:
+        u = bt.pack([p.u0 for p in probs])
+        before = u.clone()
+        c = bt.tune(u)
+        assert torch.equal(u, before)
+        assert 0 <= c.variant < fde.BATCH_VARIANTS and c.grid >= 1 and c.ms > 0
+        got = bt.get_cfg()
+        assert (got.variant, got.grid, got.lpt) == (c.variant, c.grid, c.lpt)
+        infos = bt.run(u, 1)
+    xs = bt.unpack(u)
+    for p, xg, ig in zip(probs, xs, infos[0]):
+        s = FDESystem.from_problem(p)
+        assert ig.converged
+        assert relerr(s.matvec(xg), s.rhs(p.u0)) <= 1e-8 * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("n,alpha", [(16383, 1.5), (32767, 1.8), (40000, 1.8)])
+def test_batch_full_sizes(n, alpha):
+    """Long lines: staged FFTs for the Toeplitz product and the DST, direct
+    (n + 1 = 2^k) and chirp-z (n = 40000); 16383 is the largest size of the
+    batched workload."""
+    fde = need_gpu()
+    probs = [inst(n, alpha, 1000 + n), inst(255, 1.3, 1001)]
+    xs, infos = batch_solve(probs, fde)
+    for p, xg, ig in zip(probs, xs, infos):
+        check_fp64(p, xg, ig)
