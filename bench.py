@@ -27,10 +27,141 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_2d1023_job.json")
+
+
+def class_pattern(cls):
+    """Kernel-name pattern of a probe class (the template arguments that select it)."""
+    import re
+    t = {"64": "double", "32": "float"}
+    if cls.startswith("cgs_"):
+        kind, prec = cls[4:-2], cls[-2:]
+        modes = "0" if kind == "dot" else "[12]"
+        return re.compile(rf"cgs_kernel<{t[prec]}, \d+, \d+, {modes}>")
+    if cls.startswith("line"):
+        from paper_1912_13304_amd import fde
+        prec, prog = cls[4:6], cls[7:]
+        fl = [k for k, v in fde.LINE_PROGRAMS.items() if v == prog]
+        if fl:
+            return re.compile(rf"line_kernel<{t[prec]}, (true|false), {fl[0]}, \d+>")
+    return None
+
+
+def measured_traffic(cls):
+    """HBM bytes per launch of a kernel class from the committed PMC summary,
+    or None when there is none or the HIP sources changed since it was taken."""
+    try:
+        import json as _j
+        from paper_1912_13304_amd import profsum
+        d = _j.load(open(TRAFFIC_FILE))
+        if d.get("source_hash") != profsum.source_hash():
+            return None
+        pat = class_pattern(cls)
+        if pat is None:
+            return None
+        tot, cnt = 0.0, 0
+        for name, v in d["kernels"].items():
+            if pat.search(name):
+                tot += v["traffic_bytes_avg"] * v["dispatches"]
+                cnt += v["dispatches"]
+        return tot / cnt if cnt else None
+    except (OSError, ValueError, KeyError):
+        return None
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def model_bytes_1d(n, iters, inner, m, kin, mixed):
+    """Algorithmic bytes of one 1D FGMRES(m) solve: per outer step j (mod m)
+    tau 24n + matvec 32n + CGS2 (32j + 80)n + normalisation 16n in float64;
+    the mixed form replaces the tau solve by the cast of v (12n), kin float32
+    inner steps (tau 12n, matvec 16n, CGS2 (16i + 40)n each), the inner update
+    (4(kin+1)n), the float32 tau solve (12n) and the cast back (12n)."""
+    tot = 0.0
+    for t in range(iters):
+        j = t % m
+        if mixed:
+            inner_b = sum(12 + 16 + 16 * i + 40 for i in range(kin)) + 4 * (kin + 1) + 12 + 12 + 12
+            tot += (32 + 32 * j + 80 + 16 + inner_b) * n
+        else:
+            tot += (152 + 32 * j) * n
+    return tot
+
+
+def batched_leg(args, fi, fde, torch, np):
+    """Many independent uneven 1D solves in one persistent launch per time
+    step (graph replayed per step), launch configuration picked by the tuner;
+    and the same instances solved one plan at a time for comparison."""
+    probs = fi.batched_1d(count=args.batch_count, seed=4, steps=args.batch_steps)
+    out = {"instances": len(probs), "unknowns": int(sum(p.n[0] for p in probs)),
+           "workload": f"{len(probs)} 1D instances, n log-uniform in [255, 16383] (any n), alpha ~ U(1.1,1.9), "
+                       "Example-1 coefficients x U(0.5,2), dt = h, FGMRES(30)+P_F to 1e-8, x0 = u^(m-1)"}
+    forms = {"mixed": dict(precision=fde.MIXED, inner_steps=args.inner), "fp64": dict(precision=fde.FP64)}
+    cfg = None
+    for name, kw in forms.items():
+        bt = fde.Batch(probs, **kw)
+        u = bt.pack([p.u0 for p in probs])
+        if cfg is None:
+            log(f"[bench] batched: tuning launch configuration")
+            c = bt.tune(u)
+            cfg = c.as_dict()
+        else:
+            bt.set_cfg(cfg["variant"], cfg["grid"], cfg["lpt"])
+        bt.run(u.clone(), 1, use_graph=True, allow_notconv=True)   # warm (graph captured)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = bt.run(u, args.batch_steps, use_graph=True, allow_notconv=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        its = [i.iters for st in infos for i in st]
+        inner = [i.inner_iters for st in infos for i in st]
+        mixed = name == "mixed"
+        byt = sum(model_bytes_1d(p.n[0], i.iters, 0, 30, args.inner if mixed else 0, mixed)
+                  for st in infos for p, i in zip(probs, st))
+        out[name] = dict(inst_steps_per_s=len(probs) * args.batch_steps / dt, ms_per_step=1e3 * dt / args.batch_steps,
+                         modelled_GBps=byt / dt / 1e9, iters_mean=float(np.mean(its)), iters_max=int(max(its)),
+                         inner_iters_mean=float(np.mean(inner)),
+                         all_converged=all(i.converged for st in infos for i in st),
+                         max_relres=float(max(i.relres_true for st in infos for i in st)))
+        log(f"[bench] batched {name}: {out[name]}")
+        bt.close()
+    out["cfg"] = cfg
+    # the same kind of instances, one plan at a time (float64 per-plan path; power-of-two sizes, which
+    # that path needs), against one batched launch of the same instances
+    k = min(args.batch_plan_sample, len(probs))
+    sample = fi.batched_1d(count=k, seed=4, steps=1, pow2=True)
+    plans = [fde.Plan(p) for p in sample]
+    us = [torch.as_tensor(p.u0, dtype=torch.float64, device="cuda") for p in sample]
+    bs = [torch.empty_like(u) for u in us]
+    xs = [torch.empty_like(u) for u in us]
+    for pl, u, b in zip(plans, us, bs):
+        pl.rhs(u, b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for pl, u, b, x in zip(plans, us, bs, xs):
+        x.copy_(u)
+        pl.solve(b, x, allow_notconv=True)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    for pl in plans:
+        pl.close()
+    bt = fde.Batch(sample)
+    bt.set_cfg(cfg["variant"], cfg["grid"], cfg["lpt"])
+    u = bt.pack([p.u0 for p in sample])
+    bt.run(u.clone(), 1, use_graph=False, allow_notconv=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bt.run(u, 1, use_graph=True, allow_notconv=True)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    bt.close()
+    out["vs_plan"] = {"instances": k, "plan_fp64_solves_per_s": k / t_plan, "batched_fp64_solves_per_s": k / t_batch,
+                      "speedup": t_plan / t_batch,
+                      "note": "same power-of-two-size instances, first implicit step each"}
+    log(f"[bench] batched vs plan: {out['vs_plan']}")
+    return out
 
 
 def main():
@@ -49,6 +180,12 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=500.0, help="Poisson arrival rate of the served leg")
     ap.add_argument("--serve-count", type=int, default=32, help="requests in the served leg (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--batch-count", type=int, default=512, help="instances of the batched leg (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=2, help="timed time steps of the batched leg")
+    ap.add_argument("--batch-plan-sample", type=int, default=64,
+                    help="instances solved one plan at a time for the batched-vs-plan comparison")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="run the batched leg alone (profiling); prints its JSON object")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is a design "
@@ -64,6 +201,9 @@ def main():
     fde.load()
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.only_batched:
+        print(json.dumps({"batched": batched_leg(args, fi, fde, torch, np)}), flush=True)
+        return
     prob = fi.variable_2d(n=args.n, steps=args.tsteps)
     N = prob.N
     T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev).reshape(-1).contiguous()
@@ -163,6 +303,8 @@ def main():
                           "alpha ~ U(1.1,1.9); mixed precision, tol 1e-8")
         log(f"[bench] served: {served}")
 
+    batched = batched_leg(args, fi, fde, torch, np) if args.batch_count > 0 else None
+
     # plain copy bandwidth on the same GPU (1 GiB read + 1 GiB write)
     src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
     dst = torch.empty_like(src)
@@ -181,6 +323,8 @@ def main():
     d = results[head]["dominant"]
     achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0
     avg_us = 1e3 * d["ms"] / max(1, d["launches"])
+    alg_per_launch = d["bytes"] / max(1, d["launches"])
+    traffic = measured_traffic(d["cls"])
 
     # CPU oracle on a bounded sample: the first solve of the job
     cpu = None
@@ -226,9 +370,11 @@ def main():
         "forms": results,
         "time_to_tol_ms": {k: v["ms_per_solve"] for k, v in results.items()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": d["cls"],
-                     "avg_launch_us": avg_us, "copy_GBps": copy_gbs},
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": d["cls"],
+                     "algorithmic_bytes_per_launch": alg_per_launch, "avg_launch_us": avg_us,
+                     "copy_GBps": copy_gbs},
         "served": served,
+        "batched": batched,
         "p99_served_latency_ms": served["p99_ms"] if served else None,
         "cpu_baseline": cpu,
         "parity": parity,
