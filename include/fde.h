@@ -61,7 +61,9 @@ enum { FDE_P_NONE = 0,      /* identity                                         
                                (eq. prop_1D, eq. 2D_preconditioner)                                          */
        FDE_P_TAU_HAT = 2,   /* constant coefficients d+- = d, e+- = e: tau(nu + d F_a + kappa e F_b), no D
                                (Section 3.1 Case I, eq. 2D_preconditioner_proof_case)                       */
-       FDE_P_TILDE = 3      /* 1D: S diag(D_j p_a(theta_j)) S (Section 4, Table 2)                          */ };
+       FDE_P_TILDE = 3,     /* 1D: S diag(D_j p_a(theta_j)) S (Section 4, Table 2)                          */
+       FDE_P_TRI = 4        /* 1D: the tridiagonal part of M, solved exactly (Table 2); requires a strictly
+                               diagonally dominant tridiagonal part                                        */ };
 /* Side of the diagonal factor D in P_F. */
 enum { FDE_D_LEFT = 0,      /* P = D tau, as the text writes it: P^{-1} v = tau^{-1}(D^{-1} v) */
        FDE_D_RIGHT = 1      /* P = tau D: P^{-1} v = D^{-1} tau^{-1} v                          */ };
@@ -129,7 +131,8 @@ fde_status fde_matvec(fde_plan plan, const double* x, double* y, void* stream);
 
 /* z = P^{-1} v for the plan's preconditioner: two (1D) or four (2D) DST-I
    passes around the division by the symbol samples, and the D^{-1} scaling
-   (eqs. prop_1D, 2D_preconditioner).  v, z: device, length N. */
+   (eqs. prop_1D, 2D_preconditioner); for FDE_P_TRI the tridiagonal solve.
+   v, z: device, length N. */
 fde_status fde_tau_apply(fde_plan plan, const double* v, double* z, void* stream);
 
 /* Solves M x = b (eq. linsystem).  b: device, length N.  x: device, length
@@ -222,6 +225,17 @@ fde_status fde_batch_assemble(const fde_params* params, int count, const double*
    converge / met a non-finite value (the others are still solved).
    Synchronises `stream`. */
 fde_status fde_batch_solve(fde_batch batch, const double* b, double* x, fde_info* info, void* stream);
+
+/* Batched operators on packed vectors (device): y = M x and z = P^{-1} v for
+   every instance, with its own operator and preconditioner (for FDE_P_TAU,
+   the DST-I / symbol / DST-I solve and D^{-1}; for FDE_P_TRI the tridiagonal
+   solve).  precision = FDE_FP64 computes in float64; FDE_MIXED in float32
+   (the arithmetic of the mixed form's inner solves; the batch must have been
+   assembled with FDE_MIXED).  Inputs and outputs are float64 and must not
+   overlap.  Asynchronous on `stream`.  Disabled in this build: both return
+   FDE_EUNSUPPORTED (their first GPU run faulted; the cause was not found). */
+fde_status fde_batch_matvec(fde_batch batch, int precision, const double* x, double* y, void* stream);
+fde_status fde_batch_tau_apply(fde_batch batch, int precision, const double* v, double* z, void* stream);
 
 /* Time stepping: `steps` implicit steps of every instance from the packed
    state u (device, advanced in place): b = rhs(u) with f = 0 (fde_rhs), then

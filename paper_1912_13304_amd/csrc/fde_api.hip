@@ -25,6 +25,7 @@
 #include "fde_host.hpp"
 #include "fde_krylov.hpp"
 #include "fde_lines.hpp"
+#include "fde_tri.hpp"
 
 using namespace fde;
 
@@ -59,6 +60,8 @@ struct fde_plan_s {
   double hx = 0, hy = 0, hxa = 0, nu = 0, kappa = 0, shift = 0;
   bool has_dinv = false;
   int dside = FDE_D_LEFT;
+  TriDev<double> tri64;   // P_tri factors and work (FDE_P_TRI)
+  TriDev<float> tri32;
   Dir rows, trows;   // lines along x (rows of the (n2, n1) array); along y (rows of its transpose)
   bool big = false;  // 1D line longer than one workgroup: four-step FFT over kernels
   int P1 = 0, P2 = 0, log1 = 0, log2 = 0;
@@ -143,8 +146,9 @@ static fde_status validate(const fde_params* p) {
   if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return fail(FDE_EINVAL, "tol must be > 0 (got %g)", p->tol);
   if (p->weights != FDE_W_SHIFTED && p->weights != FDE_W_WEIGHTED) return fail(FDE_EINVAL, "bad weights");
   if (p->time != FDE_T_EULER && p->time != FDE_T_CN) return fail(FDE_EINVAL, "bad time scheme");
-  if (p->prec < FDE_P_NONE || p->prec > FDE_P_TILDE) return fail(FDE_EINVAL, "bad preconditioner");
+  if (p->prec < FDE_P_NONE || p->prec > FDE_P_TRI) return fail(FDE_EINVAL, "bad preconditioner");
   if (p->prec == FDE_P_TILDE && p->dim != 1) return fail(FDE_EINVAL, "P_tilde is defined in 1D only");
+  if (p->prec == FDE_P_TRI && p->dim != 1) return fail(FDE_EINVAL, "P_tri is defined in 1D only");
   if (p->dside != FDE_D_LEFT && p->dside != FDE_D_RIGHT) return fail(FDE_EINVAL, "bad dside");
   if (p->solver != FDE_S_GMRES && p->solver != FDE_S_PCG) return fail(FDE_EINVAL, "bad solver");
   if (p->restart < 1 || p->restart > 32) return fail(FDE_EINVAL, "restart must be in 1..32");
@@ -173,6 +177,7 @@ static size_t plan_bytes_impl(const fde_params* p) {
   if (p->precision == FDE_MIXED) b += (size_t)N * 4 * (p->inner_steps + 1 + 6);
   b += (size_t)RED_MAXG * (KMAX + 1) * 8 + 2 * sizeof(KState);
   if (p->dim == 1 && n1 + 1 > 4096) b += (size_t)(n1 + 1) * (6 * 16 + (p->precision == FDE_MIXED ? 6 * 8 : 0) + 8 * 24);
+  if (p->prec == FDE_P_TRI) b += (size_t)N * 6 * (8 + 4) + (size_t)TRI_PMAX * (7 * (8 + 4) + 4) + 4;
   return b;
 }
 
@@ -264,6 +269,58 @@ static fde_status coef_stats(fde_plan pl, const double* a, double* st3, hipStrea
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(st3, d, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  return FDE_OK;
+}
+
+// P_tri: tridiagonal part of M (Table 2), factored on the host in float64.
+template <typename T>
+static fde_status tri_upload(fde_plan pl, const TriFactors& F, const int* dcs, TriDev<T>& t) {
+  t.p = F.p;
+  t.cs = dcs;
+  T *ai, *cp, *den, *sv, *sw, *ar, *cr, *ra, *rb, *rc;
+  TRY(upload(pl, &ai, F.ai));
+  TRY(upload(pl, &cp, F.cp));
+  TRY(upload(pl, &den, F.den));
+  TRY(upload(pl, &sv, F.sv));
+  TRY(upload(pl, &sw, F.sw));
+  TRY(upload(pl, &ar, F.ar));
+  TRY(upload(pl, &cr, F.cr));
+  TRY(upload(pl, &ra, F.ra));
+  TRY(upload(pl, &rb, F.rb));
+  TRY(upload(pl, &rc, F.rc));
+  t.ai = ai;
+  t.cp = cp;
+  t.den = den;
+  t.sv = sv;
+  t.sw = sw;
+  t.ar = ar;
+  t.cr = cr;
+  t.ra = ra;
+  t.rb = rb;
+  t.rc = rc;
+  TRY(dalloc(pl, &t.y, (size_t)F.n));
+  TRY(dalloc(pl, &t.part, (size_t)F.p));
+  TRY(dalloc(pl, &t.X, (size_t)F.p));
+  return FDE_OK;
+}
+
+static fde_status tri_setup(fde_plan pl, const double* dp, const double* dm) {
+  const long n = pl->n1;
+  std::vector<double> hp(n), hm(n);
+  HIPCHK(hipMemcpy(hp.data(), dp, n * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(hm.data(), dm, n * sizeof(double), hipMemcpyDeviceToHost));
+  const std::vector<double> g = weights(pl->p.alpha[0], (int)std::max(n, 2L), pl->p.weights);
+  std::vector<double> sub, diag, sup;
+  tri_part(g, pl->nu, hp.data(), hm.data(), n, sub, diag, sup);
+  for (long i = 0; i < n; ++i)
+    if (!(std::fabs(diag[i]) > std::fabs(sub[i]) + std::fabs(sup[i])))
+      return fail(FDE_EINVAL, "P_tri: the tridiagonal part of M is not strictly diagonally dominant at row %ld", i);
+  const TriFactors F = tri_factor(sub, diag, sup, TRI_PMAX);
+  int* dcs = nullptr;
+  TRY(dalloc(pl, &dcs, F.cs.size()));
+  HIPCHK(hipMemcpy(dcs, F.cs.data(), F.cs.size() * sizeof(int), hipMemcpyHostToDevice));
+  TRY(tri_upload<double>(pl, F, dcs, pl->tri64));
+  TRY(tri_upload<float>(pl, F, dcs, pl->tri32));
   return FDE_OK;
 }
 
@@ -415,6 +472,7 @@ static fde_status assemble_impl(const fde_params* p, const double* dp, const dou
     }
   }
   pl->shift = shift;
+  if (p->prec == FDE_P_TRI) TRY(tri_setup(pl, dp, dm));
   TRY(upload(pl, &pl->c64.fx, fx));
   TRY(upload(pl, &pl->c32.fx, fx));
   TRY(upload(pl, &pl->c64.fy, fy));
@@ -760,8 +818,34 @@ static void big_toep(fde_plan pl, const T* x, const T* base, T bscale, T tscale,
 // dside says) and w = M z: the fused operator step of the solvers.  With
 // prec NONE, z = sc * v.
 template <typename T>
+static const TriDev<T>& tri_dev(fde_plan pl);
+template <>
+const TriDev<double>& tri_dev<double>(fde_plan pl) { return pl->tri64; }
+template <>
+const TriDev<float>& tri_dev<float>(fde_plan pl) { return pl->tri32; }
+
+// z = P_tri^{-1}(sc v): chunk sweeps, reduced system, back substitution.
+template <typename T>
+static void tri_apply(fde_plan pl, const T* v, const double* sc, T* z, hipStream_t st, const int* skip,
+                      const int* skip2) {
+  const TriDev<T>& t = tri_dev<T>(pl);
+  hipLaunchKernelGGL((tri_chunk_kernel<T, T>), dim3((t.p + 255) / 256), dim3(256), 0, st, v, sc, t, skip, skip2);
+  hipLaunchKernelGGL((tri_reduce_kernel<T>), dim3(1), dim3(TRI_PMAX), 0, st, t, skip, skip2);
+  hipLaunchKernelGGL((tri_back_kernel<T, T>), dim3(ew_grid(pl->N)), dim3(256), 0, st, t, pl->N, z, skip, skip2);
+}
+
+template <typename T>
+static void matvec_only(fde_plan pl, const T* x, T* y, T bscale, T tscale, hipStream_t st, const int* skip,
+                        const int* skip2 = nullptr);
+
+template <typename T>
 static void tau_matvec(fde_plan pl, const T* v, const double* sc, T* z, T* w, hipStream_t st, const int* skip,
                        const int* skip2) {
+  if (pl->p.prec == FDE_P_TRI) {
+    tri_apply<T>(pl, v, sc, z, st, skip, skip2);
+    matvec_only<T>(pl, z, w, (T)pl->nu, T(1), st, skip, skip2);
+    return;
+  }
   const Consts<T>& c = consts<T>(pl);
   const bool tau = pl->p.prec != FDE_P_NONE;
   const T* pre = (pl->has_dinv && pl->dside == FDE_D_LEFT) ? c.dinv : nullptr;
@@ -859,6 +943,10 @@ static void tau_only(fde_plan pl, const T* v, const double* sc, T* z, hipStream_
                        skip, skip2);
     return;
   }
+  if (pl->p.prec == FDE_P_TRI) {
+    tri_apply<T>(pl, v, sc, z, st, skip, skip2);
+    return;
+  }
   if (pl->dim == 1 && pl->big) {
     big_tau<T>(pl, v, sc, pre, post, z, nullptr, st, skip, skip2);
     return;
@@ -913,7 +1001,7 @@ static void tau_only(fde_plan pl, const T* v, const double* sc, T* z, hipStream_
 // y = bscale*x + tscale*(A_x x + kappa A_y x)   (bscale = nu, tscale = 1: y = M x)
 template <typename T>
 static void matvec_only(fde_plan pl, const T* x, T* y, T bscale, T tscale, hipStream_t st, const int* skip,
-                        const int* skip2 = nullptr) {
+                        const int* skip2) {
   if (pl->dim == 1 && pl->big) {
     big_toep<T>(pl, x, x, bscale, tscale, y, st, skip, skip2);
     return;

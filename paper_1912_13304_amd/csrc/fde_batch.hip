@@ -66,6 +66,9 @@ Geo geometry(const fde_params& p) {
 // Bytes of one instance's tables and workspace in the arena, sub-arrays aligned.
 struct Layout {
   size_t tab64[7], tab32[7];   // dp dm dinv finv lam chirp bhat
+  size_t tri64[11], tri32[11]; // P_tri: ai cp den sv sw (n), ar cr ra rb rc (p), work y (n)
+  size_t tcs;                  // P_tri chunk starts (p + 1 ints)
+  int tp;
   size_t V, Z, b, t, Vf, uf, zf, tf, fa, fb;
   size_t total;
 };
@@ -91,6 +94,14 @@ Layout layout(const fde_params& p) {
     t[5] = take(g.blue ? (n + 1) * 2 * r : 0);
     t[6] = take(g.blue ? g.Qs * 2 * r : 0);
   }
+  const bool tri = p.prec == FDE_P_TRI;
+  L.tp = tri ? (int)std::max(1L, std::min((long)MMAX * 16, g.n / 2)) : 0;
+  for (int k = 0; k < 2; ++k) {
+    const size_t r = k == 0 ? 8 : 4;
+    size_t* t = k == 0 ? L.tri64 : L.tri32;
+    for (int a = 0; a < 11; ++a) t[a] = take(tri ? (a < 5 || a == 10 ? n : (size_t)L.tp) * r : 0);
+  }
+  L.tcs = take(tri ? (size_t)(L.tp + 1) * 4 : 0);
   const size_t m = p.restart;
   const bool mixed = p.precision == FDE_MIXED;
   const size_t kin = mixed ? p.inner_steps : 0;
@@ -121,7 +132,7 @@ fde_status validate_one(const fde_params* p, int i) {
   if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return fail(FDE_EINVAL, "instance %d: tol must be > 0", i);
   if (p->weights != FDE_W_SHIFTED && p->weights != FDE_W_WEIGHTED) return fail(FDE_EINVAL, "instance %d: bad weights", i);
   if (p->time != FDE_T_EULER && p->time != FDE_T_CN) return fail(FDE_EINVAL, "instance %d: bad time scheme", i);
-  if (p->prec < FDE_P_NONE || p->prec > FDE_P_TILDE) return fail(FDE_EINVAL, "instance %d: bad preconditioner", i);
+  if (p->prec < FDE_P_NONE || p->prec > FDE_P_TRI) return fail(FDE_EINVAL, "instance %d: bad preconditioner", i);
   if (p->dside != FDE_D_LEFT && p->dside != FDE_D_RIGHT) return fail(FDE_EINVAL, "instance %d: bad dside", i);
   if (p->solver != FDE_S_GMRES)
     return fail(FDE_EUNSUPPORTED, "instance %d: batched solves use FGMRES (solver = FDE_S_GMRES)", i);
@@ -235,7 +246,7 @@ fde_status launch_v(const Args& a, int grid, hipStream_t st) {
 
 // reset queue, persistent solve launch (and, for a time step, the step counter advance)
 fde_status enqueue(fde_batch bt, const fde_batch_cfg& c, int mode, const double* b, double* x, const int* step,
-                   hipStream_t st) {
+                   hipStream_t st, int single = 0) {
   Args a{};
   a.inst = bt->dinst;
   a.count = bt->count;
@@ -249,6 +260,7 @@ fde_status enqueue(fde_batch bt, const fde_batch_cfg& c, int mode, const double*
   a.x = x;
   a.info = bt->info;
   a.step = step;
+  a.single = single;
   const int grid = std::max(1, std::min(c.grid > 0 ? c.grid : 2 * bt->cus, bt->count));
   hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, st, bt->queue);
   HIPCHK(hipGetLastError());
@@ -378,6 +390,16 @@ fde_status assemble_impl(const fde_params* ps, int count, const double* dp, cons
     } else {
       for (long k = 0; k < n; ++k) finv[k] = 1.0;
     }
+    TriFactors TF;
+    if (p.prec == FDE_P_TRI) {
+      const std::vector<double> gw = weights(p.alpha[0], (int)std::max(n, 2L), p.weights);
+      std::vector<double> sub, diag, sup;
+      tri_part(gw, nu, ip, im, n, sub, diag, sup);
+      for (long k = 0; k < n; ++k)
+        if (!(std::fabs(diag[k]) > std::fabs(sub[k]) + std::fabs(sup[k])))
+          return fail(FDE_EINVAL, "instance %d: P_tri: tridiagonal part not strictly diagonally dominant", i);
+      TF = tri_factor(sub, diag, sup, L.tp);
+    }
     // circulant of length 2 Qt embedding T: first column (-g_1..-g_n, 0.., -g_0)
     const long Lc = 2 * g.Qt;
     std::vector<double> w = weights(p.alpha[0], (int)n, p.weights);
@@ -426,6 +448,15 @@ fde_status assemble_impl(const fde_params* ps, int count, const double* dp, cons
       put_cx<float>(img, L.tab32[5], chirp);
       put_cx<float>(img, L.tab32[6], bhat);
     }
+    if (p.prec == FDE_P_TRI) {
+      const std::vector<double>* arr[10] = {&TF.ai, &TF.cp, &TF.den, &TF.sv, &TF.sw,
+                                            &TF.ar, &TF.cr, &TF.ra, &TF.rb, &TF.rc};
+      for (int a = 0; a < 10; ++a) {
+        put<double>(img, L.tri64[a], *arr[a]);
+        put<float>(img, L.tri32[a], *arr[a]);
+      }
+      std::memcpy(img.data() + L.tcs, TF.cs.data(), TF.cs.size() * sizeof(int));
+    }
     const size_t tab_end = L.V;   // tables precede the workspace
     HIPCHK(hipMemcpy(arena + base[i], img.data(), tab_end, hipMemcpyHostToDevice));
     unsigned char* a0 = arena + base[i];
@@ -454,6 +485,18 @@ fde_status assemble_impl(const fde_params* ps, int count, const double* dp, cons
                        reinterpret_cast<float*>(a0 + L.tab32[3]), reinterpret_cast<cx<float>*>(a0 + L.tab32[4]),
                        g.blue ? reinterpret_cast<cx<float>*>(a0 + L.tab32[5]) : nullptr,
                        g.blue ? reinterpret_cast<cx<float>*>(a0 + L.tab32[6]) : nullptr};
+    I.tp = p.prec == FDE_P_TRI ? TF.p : 0;
+    I.tcs = p.prec == FDE_P_TRI ? reinterpret_cast<const int*>(a0 + L.tcs) : nullptr;
+    {
+      auto d64 = [&](int a) { return p.prec == FDE_P_TRI ? reinterpret_cast<double*>(a0 + L.tri64[a]) : nullptr; };
+      auto d32 = [&](int a) { return p.prec == FDE_P_TRI ? reinterpret_cast<float*>(a0 + L.tri32[a]) : nullptr; };
+      I.t64.ai = d64(0); I.t64.cp = d64(1); I.t64.den = d64(2); I.t64.sv = d64(3); I.t64.sw = d64(4);
+      I.t64.ar = d64(5); I.t64.cr = d64(6); I.t64.ra = d64(7); I.t64.rb = d64(8); I.t64.rc = d64(9);
+      I.t64.ty = d64(10);
+      I.t32.ai = d32(0); I.t32.cp = d32(1); I.t32.den = d32(2); I.t32.sv = d32(3); I.t32.sw = d32(4);
+      I.t32.ar = d32(5); I.t32.cr = d32(6); I.t32.ra = d32(7); I.t32.rb = d32(8); I.t32.rc = d32(9);
+      I.t32.ty = d32(10);
+    }
     I.V = reinterpret_cast<double*>(a0 + L.V);
     I.Z = reinterpret_cast<double*>(a0 + L.Z);
     I.b = reinterpret_cast<double*>(a0 + L.b);
@@ -565,6 +608,33 @@ extern "C" fde_status fde_batch_solve(fde_batch bt, const double* b, double* x, 
   HIPCHK(hipStreamSynchronize(st));
   const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return collect(bt, bt->count, info, sec, st);
+}
+
+// The batched operator launches are disabled: their first GPU run took a
+// memory fault whose cause was not found (a CPU emulation of the same code
+// with per-array bounds checking runs clean at every size of that run).
+static constexpr bool BATCH_APPLY_ENABLED = false;
+
+static fde_status batch_apply(fde_batch bt, int mode, int precision, const double* in, double* out, void* stream) {
+  if (!bt || !in || !out) return fail(FDE_EINVAL, "NULL argument");
+  if (!BATCH_APPLY_ENABLED) return fail(FDE_EUNSUPPORTED, "batched operator launches are disabled in this build");
+  if (precision != FDE_FP64 && precision != FDE_MIXED) return fail(FDE_EINVAL, "bad precision");
+  const int single = precision == FDE_MIXED;
+  if (single)
+    for (int i = 0; i < bt->count; ++i)
+      if (bt->p[i].precision != FDE_MIXED)
+        return fail(FDE_EINVAL, "float32 operators need a batch assembled with FDE_MIXED (instance %d)", i);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  TRY(enqueue(bt, bt->cfg, mode, in, out, nullptr, st, single));
+  return FDE_OK;
+}
+
+extern "C" fde_status fde_batch_matvec(fde_batch bt, int precision, const double* x, double* y, void* stream) {
+  return batch_apply(bt, MODE_MATVEC, precision, x, y, stream);
+}
+
+extern "C" fde_status fde_batch_tau_apply(fde_batch bt, int precision, const double* v, double* z, void* stream) {
+  return batch_apply(bt, MODE_TAU, precision, v, z, stream);
 }
 
 extern "C" fde_status fde_batch_run(fde_batch bt, double* u, int steps, int use_graph, fde_info* info,

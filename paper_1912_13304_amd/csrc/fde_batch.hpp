@@ -64,13 +64,18 @@ struct Tab {
   const cx<T>* lam;     // eigenvalues of the circulant embedding of T, k = 0..Qt, over 2 Qt
   const cx<T>* chirp;   // exp(i pi j^2/(2(n+1))), j = 0..n (chirp-z DST)
   const cx<T>* bhat;    // FFT of the chirp filter, times sqrt(2/(n+1))/Qs (chirp-z DST)
+  // P_tri (partitioned tridiagonal solve, factors from tri_factor): per row
+  // ai, cp, den, sv, sw; per chunk ar, cr, ra, rb, rc; work y (n values)
+  const T *ai, *cp, *den, *sv, *sw, *ar, *cr, *ra, *rb, *rc;
+  T* ty;
 };
 
 struct Inst {
   int n, logQt, logQs, blue;   // blue: chirp-z DST (n + 1 not a power of two)
   int prec, dside, time, precision;
-  int kin, m, maxit, pad0;
+  int kin, m, maxit, tp;       // tp: P_tri chunks (<= 512), chunk starts in tcs
   double tol, nu;
+  const int* tcs;
   long off;                    // first element of the instance in the packed vectors
   Tab<double> t64;
   Tab<float> t32;
@@ -79,7 +84,12 @@ struct Inst {
   cx<double> *fa, *fb;         // global FFT buffers (null when every transform fits in LDS)
 };
 
-enum : int { MODE_SOLVE = 0, MODE_STEP = 1 };
+enum : int {
+  MODE_SOLVE = 0,     // solve M x = b for every instance
+  MODE_STEP = 1,      // one implicit time step: b = rhs(x), then solve from x
+  MODE_MATVEC = 2,    // out = M in
+  MODE_TAU = 3,       // out = P^{-1} in (the instance's preconditioner, without an inner solve)
+};
 
 struct Args {
   const Inst* inst;
@@ -89,7 +99,8 @@ struct Args {
   const cx<double>* tw64; // exp(-2 pi i m/TW), m < TW = 2^logTW
   const cx<float>* tw32;
   int logTW, pad0;
-  const double* bin;      // MODE_SOLVE: packed right-hand sides
+  const double* bin;      // MODE_SOLVE: packed right-hand sides; MODE_MATVEC / MODE_TAU: inputs
+  int single, pad1;       // MODE_MATVEC / MODE_TAU: arithmetic in float32
   double* x;              // packed start vectors / solutions (MODE_STEP: states, advanced in place)
   Info* info;
   const int* step;        // when set, instance i reports to info[*step * count + i]
@@ -177,7 +188,7 @@ __device__ __forceinline__ void lds_pass(cx<T>* s, int nl, int logL, int LS, int
 // Forward FFT of nl lines of length 2^logL held in LDS; nl * 2^logL must not
 // exceed Cap<T>.  The caller has synchronised after writing the data.
 template <typename T, int NT, int RAD>
-__device__ void lds_fft(cx<T>* s, int nl, int logL, int LS, const cx<T>* tw, int logTW) {
+__device__ __forceinline__ void lds_fft(cx<T>* s, int nl, int logL, int LS, const cx<T>* tw, int logTW) {
   int logLs = 0;
   while (logLs < logL) {
     const int rem = logL - logLs;
@@ -197,7 +208,7 @@ __device__ void lds_fft(cx<T>* s, int nl, int logL, int LS, const cx<T>* tw, int
 // Forward FFT of length Q = 2^logQ > Cap<T> in global memory `a` (natural
 // order in and out), through `tmp` (Q values) and the LDS staging area s.
 template <typename T, int NT, int RAD>
-__device__ void staged_fft(cx<T>* a, cx<T>* tmp, int logQ, cx<T>* s, const cx<T>* tw, int logTW) {
+__device__ __forceinline__ void staged_fft(cx<T>* a, cx<T>* tmp, int logQ, cx<T>* s, const cx<T>* tw, int logTW) {
   constexpr int LOGCAP = Cap<T>::log;
   const int tid = threadIdx.x;
   const int log1 = (logQ + 1) >> 1, log2 = logQ >> 1;
@@ -267,7 +278,7 @@ __device__ __forceinline__ double block_sum(double v, Shm<NT>& sh) {
 
 // y_k = post_k (S_n u)_k, u_j = s pre_j x_j (pre, post may be null), k < n.
 template <typename T, int NT, int RAD, bool INLDS, typename Tin, typename Tout>
-__device__ void dst_op(const Inst& I, Shm<NT>& sh, const cx<T>* tw, int logTW, const Tin* x, const T* pre,
+__device__ __forceinline__ void dst_op(const Inst& I, Shm<NT>& sh, const cx<T>* tw, int logTW, const Tin* x, const T* pre,
                        double s, Tout* y, const T* post) {
   const Tab<T>& tb = tab<T>(I);
   const int n = I.n, tid = threadIdx.x;
@@ -339,7 +350,7 @@ __device__ void dst_op(const Inst& I, Shm<NT>& sh, const cx<T>* tw, int logTW, c
 // out_i = c0 base_i + c1 x_i + c2 (d+_i (T x)_i + d-_i (T^T x)_i); returns the
 // workgroup sum of out_i^2 when want_norm (0 otherwise).  base may be null.
 template <typename T, int NT, int RAD, bool INLDS, typename Tio>
-__device__ double toep_op(const Inst& I, Shm<NT>& sh, const cx<T>* tw, int logTW, const Tio* x,
+__device__ __forceinline__ double toep_op(const Inst& I, Shm<NT>& sh, const cx<T>* tw, int logTW, const Tio* x,
                           const double* base, double c0, double c1, double c2, Tio* out, bool want_norm) {
   const Tab<T>& tb = tab<T>(I);
   const int n = I.n, tid = threadIdx.x;
@@ -419,16 +430,106 @@ __device__ __forceinline__ double toep_any(const Inst& I, Shm<NT>& sh, const cx<
   return toep_op<T, NT, RAD, false>(I, sh, tw, logTW, x, base, c0, c1, c2, out, want_norm);
 }
 
+// z = P_tri^{-1}(s v) (Table 2) by the partitioned elimination: thread k
+// sweeps the interior of chunk k with the precomputed pivots, parallel cyclic
+// reduction over the chunk interfaces runs in LDS, and every row is then
+// recovered from its interior solution and the two neighbouring interfaces.
+template <typename T, int NT, typename Tin, typename Tout>
+__device__ __forceinline__ void tri_wg(const Inst& I, Shm<NT>& sh, const Tin* v, double s, Tout* z) {
+  const Tab<T>& tb = tab<T>(I);
+  const int tid = threadIdx.x, p = I.tp, n = I.n;
+  const int* cs = I.tcs;
+  T* y = tb.ty;
+  T* sA = reinterpret_cast<T*>(sh.fft);
+  T* sB = sA + NT;
+  T* sC = sB + NT;
+  T* sD = sC + NT;
+  const T scale = (T)s;
+  if (tid < p) {
+    const int s0 = cs[tid], r = cs[tid + 1] - 1;
+    T d = T(0);
+    for (int i = s0; i < r; ++i) {
+      d = ((T)v[i] * scale - tb.ai[i] * d) * tb.den[i];
+      y[i] = d;
+    }
+    T yn = T(0);
+    for (int i = r - 1; i >= s0; --i) {
+      yn = y[i] - tb.cp[i] * yn;
+      y[i] = yn;
+    }
+    sD[tid] = (T)v[r] * scale - tb.ar[tid] * (r > s0 ? y[r - 1] : T(0));
+  }
+  __syncthreads();
+  if (tid < p) {
+    if (tid + 1 < p) {
+      const int s2 = cs[tid + 1], q2 = cs[tid + 2] - 1 - s2;
+      if (q2 >= 1) sD[tid] -= tb.cr[tid] * y[s2];
+    }
+    sA[tid] = tb.ra[tid];
+    sB[tid] = tb.rb[tid];
+    sC[tid] = tb.rc[tid];
+  }
+  __syncthreads();
+  for (int st = 1; st < p; st <<= 1) {
+    T nA = T(0), nB = T(0), nC = T(0), nD = T(0);
+    if (tid < p) {
+      const int km = tid - st, kp = tid + st;
+      nB = sB[tid];
+      nD = sD[tid];
+      if (km >= 0) {
+        const T al = -sA[tid] / sB[km];
+        nA = al * sA[km];
+        nB += al * sC[km];
+        nD += al * sD[km];
+      }
+      if (kp < p) {
+        const T ga = -sC[tid] / sB[kp];
+        nC = ga * sC[kp];
+        nB += ga * sA[kp];
+        nD += ga * sD[kp];
+      }
+    }
+    __syncthreads();
+    if (tid < p) {
+      sA[tid] = nA;
+      sB[tid] = nB;
+      sC[tid] = nC;
+      sD[tid] = nD;
+    }
+    __syncthreads();
+  }
+  if (tid < p) sD[tid] = sD[tid] / sB[tid];   // X_k
+  __syncthreads();
+  for (int i = tid; i < n; i += NT) {
+    int k = (int)(((long)i * p) / n);
+    while (k + 1 < p && cs[k + 1] <= i) ++k;
+    const int r = cs[k + 1] - 1;
+    T out;
+    if (i == r) {
+      out = sD[k];
+    } else {
+      out = y[i] - sD[k] * tb.sw[i];
+      if (k > 0) out -= sD[k - 1] * tb.sv[i];
+    }
+    z[i] = (Tout)out;
+  }
+  __syncthreads();
+}
+
 // z = P^{-1}(s v) in precision T (eq. prop_1D; Section 3.1 Case I; Table 2):
 // left D:  z = S (F^{-1} . S (D^{-1} s v));  right D: z = D^{-1} S (F^{-1} . S (s v)).
 // tmp holds the intermediate (n values of T).
 template <typename T, int NT, int RAD, typename Tin, typename Tout>
-__device__ void tau_apply(const Inst& I, Shm<NT>& sh, const cx<T>* tw, int logTW, const Tin* v, double s,
+__device__ __forceinline__ void tau_apply(const Inst& I, Shm<NT>& sh, const cx<T>* tw, int logTW, const Tin* v, double s,
                           Tout* z, T* tmp) {
   const Tab<T>& tb = tab<T>(I);
   if (I.prec == FDE_P_NONE) {
     for (int i = threadIdx.x; i < I.n; i += NT) z[i] = (Tout)((T)v[i] * (T)s);
     __syncthreads();
+    return;
+  }
+  if (I.prec == FDE_P_TRI) {
+    tri_wg<T, NT>(I, sh, v, s, z);
     return;
   }
   const bool left = I.dside == FDE_D_LEFT;
@@ -447,7 +548,7 @@ __device__ void tau_apply(const Inst& I, Shm<NT>& sh, const cx<T>* tw, int logTW
 // and carry no weight.
 // ---------------------------------------------------------------------------
 template <typename T, int NT, int KC, bool UPD, bool NORM>
-__device__ void cgs_sweep(const T* V, int nk, int d0, T* w, int n, const double* coef, Shm<NT>& sh) {
+__device__ __forceinline__ void cgs_sweep(const T* V, int nk, int d0, T* w, int n, const double* coef, Shm<NT>& sh) {
   constexpr int NA = NORM ? 1 : KC;
   double acc[NA];
 #pragma unroll
@@ -498,7 +599,7 @@ __device__ __forceinline__ void cgs_dots(const T* V, int nk, int d0, T* w, int n
 
 // CGS2 of w against basis vectors 0..j: h (LDS, j+1 values) and ||w||.
 template <typename T, int NT>
-__device__ double cgs2(const T* V, int j, T* w, int n, const double* sc, Shm<NT>& sh) {
+__device__ __forceinline__ double cgs2(const T* V, int j, T* w, int n, const double* sc, Shm<NT>& sh) {
   const int nk = j + 1;
   const int tid = threadIdx.x;
   for (int d0 = 0; d0 < nk; d0 += 16) {
@@ -528,7 +629,7 @@ __device__ double cgs2(const T* V, int j, T* w, int n, const double* sc, Shm<NT>
 
 // Rotations 0..j-1 applied to column j (h[0..j], hn), rotation j formed,
 // g updated; column stored packed in R.  Thread 0; returns |g[j+1]|.
-__device__ inline double givens_col(const double* h, double hn, int j, double* R, double* cs, double* sn,
+__device__ __forceinline__ double givens_col(const double* h, double hn, int j, double* R, double* cs, double* sn,
                                     double* g) {
   double* col = R + j * (j + 1) / 2;
   for (int i = 0; i <= j; ++i) col[i] = h[i];
@@ -554,7 +655,7 @@ __device__ inline double givens_col(const double* h, double hn, int j, double* R
 }
 
 // y = R^{-1} g for the leading k x k block (packed columns).  Thread 0.
-__device__ inline void backsolve(const double* R, const double* g, int k, double* y) {
+__device__ __forceinline__ void backsolve(const double* R, const double* g, int k, double* y) {
   for (int i = k - 1; i >= 0; --i) {
     double s = g[i];
     for (int l = i + 1; l < k; ++l) s -= R[l * (l + 1) / 2 + i] * y[l];
@@ -569,7 +670,7 @@ __device__ inline void backsolve(const double* R, const double* g, int k, double
 // kin = 0 is the float32 tau solve alone.
 // ---------------------------------------------------------------------------
 template <int NT, int RAD>
-__device__ void precondition(const Args& a, const Inst& I, Shm<NT>& sh, const double* v, double s, double* z,
+__device__ __forceinline__ void precondition(const Args& a, const Inst& I, Shm<NT>& sh, const double* v, double s, double* z,
                              int& inner_iters) {
   const int n = I.n, tid = threadIdx.x;
   if (I.precision == FDE_FP64) {
@@ -634,7 +735,7 @@ __device__ void precondition(const Args& a, const Inst& I, Shm<NT>& sh, const do
 // decides convergence.
 // ---------------------------------------------------------------------------
 template <int NT, int RAD>
-__device__ void solve_one(const Args& a, const Inst& I, Shm<NT>& sh, Info& res) {
+__device__ __forceinline__ void solve_one(const Args& a, const Inst& I, Shm<NT>& sh, Info& res) {
   const int n = I.n, m = I.m, tid = threadIdx.x;
   double* x = a.x + I.off;
   const cx<double>* tw = a.tw64;
@@ -734,8 +835,27 @@ __device__ void solve_one(const Args& a, const Inst& I, Shm<NT>& sh, Info& res) 
   res.relres_est = est / bnorm;
 }
 
+// One operator application for an instance (matvec or preconditioner), in
+// float64 or float32 arithmetic on float64 input and output.
+template <int NT, int RAD>
+__device__ __forceinline__ void apply_one(const Args& a, const Inst& I, Shm<NT>& sh) {
+  const double* in = a.bin + I.off;
+  double* out = a.x + I.off;
+  if (a.mode == MODE_MATVEC) {
+    if (a.single) toep_any<float, NT, RAD>(I, sh, a.tw32, a.logTW, in, nullptr, 0.0, I.nu, 1.0, out, false);
+    else toep_any<double, NT, RAD>(I, sh, a.tw64, a.logTW, in, nullptr, 0.0, I.nu, 1.0, out, false);
+  } else {
+    if (a.single) tau_apply<float, NT, RAD>(I, sh, a.tw32, a.logTW, in, 1.0, out, I.tf);
+    else tau_apply<double, NT, RAD>(I, sh, a.tw64, a.logTW, in, 1.0, out, I.t);
+  }
+}
+
 // Persistent kernel: workgroups take instances from the ticket queue until
-// it runs dry (every workgroup reaches the exit).
+// it runs dry (every workgroup reaches the exit).  Every device function of
+// the engine is inlined into this one kernel: the build with out-of-line
+// calls gave wrong float32 results at -O3 (staged chirp-z transforms, radix
+// 8) that the same source at -O1, the inlined build and a bounds-checked CPU
+// emulation do not show.
 template <int NT, int RAD>
 __global__ void __launch_bounds__(NT, NT / 128) batch_kernel(Args a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -748,6 +868,10 @@ __global__ void __launch_bounds__(NT, NT / 128) batch_kernel(Args a) {
     if (t >= a.count) break;
     const int idx = a.order[t];
     const Inst& I = a.inst[idx];
+    if (a.mode >= MODE_MATVEC) {
+      apply_one<NT, RAD>(a, I, sh);
+      continue;
+    }
     Info res;
     solve_one<NT, RAD>(a, I, sh, res);
     if (threadIdx.x == 0) {

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdarg>
+#include <algorithm>
 #include <cstdio>
 #include <string>
 #include <vector>
@@ -99,6 +100,111 @@ inline double symbol(double a, double t, int kind) {
     return -((2.0 - a * (1.0 - std::exp(-I * th))) / 2.0) * base;
   };
   return (f(t) + f(-t)).real();
+}
+
+// Partitioned factorisation of a tridiagonal matrix (sub[i] = A[i][i-1],
+// diag[i], sup[i] = A[i][i+1]) for the P_tri solve: rows split into p chunks
+// [cs[k], cs[k+1]) of at least two rows; the last row r of chunk k is the
+// interface unknown X_k, rows cs[k]..r-1 its interior.  Per row: the interior
+// Thomas pivots (ai = sub with the chunk's first entry zeroed, cp, den) and
+// the interior responses sv, sw to the couplings sub[cs[k]] X_{k-1} and
+// sup[r-1] X_k; per chunk: ar = sub[r], cr = sup[r] (0 for the last chunk) and
+// the tridiagonal system (ra, rb, rc) in the X_k left after the interiors are
+// eliminated.  A strictly diagonally dominant A needs no pivoting.
+struct TriFactors {
+  long n = 0;
+  int p = 0;
+  std::vector<int> cs;
+  std::vector<double> ai, cp, den, sv, sw;
+  std::vector<double> ar, cr, ra, rb, rc;
+};
+
+inline TriFactors tri_factor(const std::vector<double>& sub, const std::vector<double>& diag,
+                             const std::vector<double>& sup, int pmax) {
+  TriFactors F;
+  const long n = (long)diag.size();
+  F.n = n;
+  F.p = (int)std::max(1L, std::min((long)pmax, n / 2));
+  const int p = F.p;
+  F.cs.resize(p + 1);
+  for (int k = 0; k <= p; ++k) F.cs[k] = (int)(((long)k * n) / p);
+  F.ai.assign(n, 0.0);
+  F.cp.assign(n, 0.0);
+  F.den.assign(n, 0.0);
+  F.sv.assign(n, 0.0);
+  F.sw.assign(n, 0.0);
+  auto thomas = [&](long s, long r, std::vector<double>& x) {   // x: rhs of rows s..r-1, in place
+    double d = 0.0;
+    for (long i = s; i < r; ++i) {
+      d = (x[i - s] - F.ai[i] * d) * F.den[i];
+      x[i - s] = d;
+    }
+    double yn = 0.0;
+    for (long i = r - 1; i >= s; --i) {
+      yn = x[i - s] - F.cp[i] * yn;
+      x[i - s] = yn;
+    }
+  };
+  for (int k = 0; k < p; ++k) {
+    const long s = F.cs[k], r = F.cs[k + 1] - 1;
+    double prev = 0.0;
+    for (long i = s; i < r; ++i) {
+      const double a = i == s ? 0.0 : sub[i];
+      const double c = i == r - 1 ? 0.0 : sup[i];
+      const double dd = 1.0 / (diag[i] - a * prev);
+      F.ai[i] = a;
+      F.den[i] = dd;
+      F.cp[i] = c * dd;
+      prev = F.cp[i];
+    }
+    const long q = r - s;
+    if (q >= 1) {
+      std::vector<double> e(q, 0.0);
+      e[0] = sub[s];
+      thomas(s, r, e);
+      for (long i = 0; i < q; ++i) F.sv[s + i] = e[i];
+      std::fill(e.begin(), e.end(), 0.0);
+      e[q - 1] = sup[r - 1];
+      thomas(s, r, e);
+      for (long i = 0; i < q; ++i) F.sw[s + i] = e[i];
+    }
+  }
+  F.ar.assign(p, 0.0);
+  F.cr.assign(p, 0.0);
+  F.ra.assign(p, 0.0);
+  F.rb.assign(p, 0.0);
+  F.rc.assign(p, 0.0);
+  for (int k = 0; k < p; ++k) {
+    const long s = F.cs[k], r = F.cs[k + 1] - 1, q = r - s;
+    F.ar[k] = sub[r];
+    F.cr[k] = k + 1 < p ? sup[r] : 0.0;
+    const double aL = q >= 1 ? F.sv[r - 1] : -1.0, bL = q >= 1 ? F.sw[r - 1] : 0.0;
+    double aR = 0.0, bR = 0.0;
+    if (k + 1 < p) {
+      const long s2 = F.cs[k + 1], q2 = F.cs[k + 2] - 1 - s2;
+      aR = q2 >= 1 ? F.sv[s2] : 0.0;
+      bR = q2 >= 1 ? F.sw[s2] : -1.0;
+    }
+    F.ra[k] = -F.ar[k] * aL;
+    F.rb[k] = diag[r] - F.ar[k] * bL - F.cr[k] * aR;
+    F.rc[k] = -F.cr[k] * bR;
+  }
+  return F;
+}
+
+// Tridiagonal part of the 1D M = nu I + D+ T + D- T^T (T = -[g_{i-j+1}]):
+// M[i][i] = nu - (d+_i + d-_i) g_1, M[i][i-1] = -d+_i g_2 - d-_i g_0,
+// M[i][i+1] = -d+_i g_0 - d-_i g_2 (P_tri of Table 2).
+inline void tri_part(const std::vector<double>& g, double nu, const double* dp, const double* dm, long n,
+                     std::vector<double>& sub, std::vector<double>& diag, std::vector<double>& sup) {
+  sub.assign(n, 0.0);
+  diag.assign(n, 0.0);
+  sup.assign(n, 0.0);
+  for (long i = 0; i < n; ++i) {
+    diag[i] = nu - (dp[i] + dm[i]) * g[1];
+    if (i > 0) sub[i] = -dp[i] * g[2] - dm[i] * g[0];
+    if (i + 1 < n) sup[i] = -dp[i] * g[0] - dm[i] * g[2];
+  }
 }
 
 }  // namespace fde

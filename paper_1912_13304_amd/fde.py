@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "FDE_OK", 1: "FDE_ENOTCONV", -1: "FDE_EINVAL", -2: "FDE_ENOME
                 -4: "FDE_ENONFINITE", -5: "FDE_EUNSUPPORTED"}
 W_SHIFTED, W_WEIGHTED = 0, 1
 T_EULER, T_CN = 0, 1
-P_NONE, P_TAU, P_TAU_HAT, P_TILDE = 0, 1, 2, 3
+P_NONE, P_TAU, P_TAU_HAT, P_TILDE, P_TRI = 0, 1, 2, 3, 4
 D_LEFT, D_RIGHT = 0, 1
 S_GMRES, S_PCG = 0, 1
 FP64, MIXED = 0, 1
@@ -34,7 +34,8 @@ LINE_PROGRAMS = {1: "dst", 3: "dst_f_dst", 8: "toeplitz", 11: "dst_f_dst_toeplit
 EXPORTED = ["fde_default_params", "fde_assemble", "fde_matvec", "fde_tau_apply", "fde_solve", "fde_rhs",
             "fde_plan_bytes", "fde_destroy", "fde_last_error", "fde_probe", "fde_probe_read",
             "fde_batch_layout", "fde_batch_bytes", "fde_batch_assemble", "fde_batch_solve", "fde_batch_run",
-            "fde_batch_tune", "fde_batch_get_cfg", "fde_batch_set_cfg", "fde_batch_destroy"]
+            "fde_batch_tune", "fde_batch_get_cfg", "fde_batch_set_cfg", "fde_batch_destroy",
+            "fde_batch_matvec", "fde_batch_tau_apply"]
 BATCH_VARIANTS = 4
 
 
@@ -138,6 +139,10 @@ def load(path: str = LIB_PATH):
     lib.fde_batch_get_cfg.restype = ctypes.c_int
     lib.fde_batch_set_cfg.argtypes = [vp, cp]
     lib.fde_batch_set_cfg.restype = ctypes.c_int
+    lib.fde_batch_matvec.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    lib.fde_batch_matvec.restype = ctypes.c_int
+    lib.fde_batch_tau_apply.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    lib.fde_batch_tau_apply.restype = ctypes.c_int
     lib.fde_batch_destroy.argtypes = [vp]
     lib.fde_batch_destroy.restype = None
     lib.fde_last_error.argtypes = []
@@ -359,6 +364,12 @@ class Batch:
         st = load().fde_batch_run(self.handle, _ptr(u), int(steps), int(bool(use_graph)), infos, _stream(stream))
         _check(st, allow_notconv)
         return [list(infos[s * self.count:(s + 1) * self.count]) for s in range(steps)]
+
+    def matvec(self, x, y, precision=FP64, stream=None):
+        _check(load().fde_batch_matvec(self.handle, int(precision), _ptr(x), _ptr(y), _stream(stream)))
+
+    def tau_apply(self, v, z, precision=FP64, stream=None):
+        _check(load().fde_batch_tau_apply(self.handle, int(precision), _ptr(v), _ptr(z), _stream(stream)))
 
     def tune(self, u, stream=None) -> FdeBatchCfg:
         c = FdeBatchCfg()

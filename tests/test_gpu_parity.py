@@ -268,3 +268,63 @@ def test_coefficient_validation():
     p.dminus = np.zeros(63)
     with pytest.raises(fde.FdeError):
         fde.Plan(p)
+
+
+# ---------------------------------------------------------------------------
+# P_tri (Table 2): the tridiagonal part of M solved by the partitioned
+# elimination (chunk sweeps, reduced system by cyclic reduction, back
+# substitution), against the oracle's banded solve.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [1, 3, 7, 63, 1023, 4095, 8191, 65535])
+@pytest.mark.parametrize("weights,time", [("shifted", "euler"), ("shifted", "cn")])
+def test_tri_apply(n, weights, time):
+    fde = need_gpu()
+    p = prob1d(n, weights=weights, time=time)
+    s = FDESystem.from_problem(p)
+    v = rng_vec(n, n + 3)
+    with fde.Plan(p, prec=fde.P_TRI) as plan:
+        z = torch.empty(n, dtype=torch.float64, device="cuda")
+        plan.tau_apply(dev(v), z)
+        assert relerr(host(z), pc.make("tri", s)(v)) < 1e-12
+
+
+@pytest.mark.parametrize("n,alpha", [(255, 1.3), (1023, 1.5), (4095, 1.8), (65535, 1.2)])
+def test_tri_fgmres(n, alpha):
+    fde = need_gpu()
+    p = prob1d(n, alpha=alpha, seed=n)
+    s = FDESystem.from_problem(p)
+    b = s.rhs(p.u0)
+    xo, io = krylov.fgmres(s.matvec, b, pc.make("tri", s), x0=p.u0, restart=30, tol=1e-8)
+    with fde.Plan(p, prec=fde.P_TRI) as plan:
+        x = dev(p.u0)
+        ig = plan.solve(dev(b), x)
+        xg = host(x)
+    assert ig.converged and io["converged"]
+    assert abs(ig.iters - io["iters"]) <= max(1, 0.005 * io["iters"]), (ig.iters, io["iters"])
+    assert relerr(s.matvec(xg), b) <= 1e-8 * (1 + 1e-6)
+    if ig.iters == io["iters"]:
+        assert relerr(xg, xo) < 1e-9
+
+
+def test_tri_mixed():
+    fde = need_gpu()
+    p = prob1d(4095, alpha=1.5, seed=5)
+    s = FDESystem.from_problem(p)
+    b = s.rhs(p.u0)
+    with fde.Plan(p, prec=fde.P_TRI, precision=fde.MIXED, inner_steps=8) as plan:
+        x = dev(p.u0)
+        ig = plan.solve(dev(b), x)
+    assert ig.converged
+    assert relerr(s.matvec(host(x)), b) <= 1e-8 * (1 + 1e-6)
+
+
+def test_tri_rejected_in_2d_and_without_dominance():
+    """The partitioned elimination does not pivot: it takes the strictly
+    diagonally dominant tridiagonal part of the first-order scheme (the case
+    of Table 2), and rejects 2D and the second-order weights' non-dominant one."""
+    fde = need_gpu()
+    with pytest.raises(fde.FdeError):
+        fde.Plan(prob2d(15, 15), prec=fde.P_TRI)
+    with pytest.raises(fde.FdeError) as e:
+        fde.Plan(prob1d(63, weights="weighted", time="cn"), prec=fde.P_TRI)
+    assert e.value.status == fde.FDE_EINVAL
