@@ -164,6 +164,91 @@ def batched_leg(args, fi, fde, torch, np):
     return out
 
 
+def _first_step(fde, torch, p, kw, reps=2):
+    """First implicit step of problem p on the plan path: (iterations, ms per solve, converged)."""
+    T = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda").reshape(-1).contiguous()
+    with fde.Plan(p, **kw) as plan:
+        u = T(p.u0)
+        b = torch.empty_like(u)
+        plan.rhs(u, b)
+        best, info = 1e30, None
+        for _ in range(reps):
+            x = u.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = plan.solve(b, x, allow_notconv=True)
+            best = min(best, time.perf_counter() - t0)
+    return info.iters, 1e3 * best, bool(info.converged)
+
+
+def table_variants(fi, fde, torch, np):
+    """Preconditioner variants on the first implicit step of the 1D (n = 65535)
+    and 2D (1023^2) workloads: P_F with D on either side, P_tilde, P_tri, and
+    P_F with the symbol shifted by nu/mean(D) (a variant the paper does not use
+    for variable coefficients), FGMRES(30) to 1e-8, float64 plan path."""
+    rows = []
+    for alpha in (1.2, 1.5, 1.8):
+        p = fi.variable_1d(n=65535, alpha=alpha, steps=1)
+        h = p.h[0]
+        nu = h ** alpha / p.dt
+        shift = nu / float(np.mean(0.5 * (p.dplus + p.dminus)))
+        forms = [("P_F D.tau (text)", dict(prec=fde.P_TAU, dside=fde.D_LEFT)),
+                 ("P_F tau.D (tables)", dict(prec=fde.P_TAU, dside=fde.D_RIGHT)),
+                 ("P_tilde", dict(prec=fde.P_TILDE)),
+                 ("P_tri", dict(prec=fde.P_TRI)),
+                 ("P_F D.tau + nu/mean(D) (not in the paper)", dict(prec=fde.P_TAU, dside=fde.D_LEFT, shift=shift))]
+        for name, kw in forms:
+            it, ms, conv = _first_step(fde, torch, p, dict(maxit=20000, **kw))
+            rows.append({"workload": f"1D n=65535 alpha={alpha}", "preconditioner": name, "iters": it,
+                         "ms": ms, "converged": conv})
+            log(f"[table] {rows[-1]}")
+    p = fi.variable_2d(n=1023, steps=1)
+    nu = p.h[0] ** p.alpha[0] / p.dt
+    shift = nu / float(np.mean(0.25 * (p.dplus + p.dminus + p.eplus + p.eminus)))
+    for name, kw in [("P_F D.tau (text)", dict(prec=fde.P_TAU, dside=fde.D_LEFT)),
+                     ("P_F tau.D (tables)", dict(prec=fde.P_TAU, dside=fde.D_RIGHT)),
+                     ("P_F D.tau + nu/mean(D) (not in the paper)", dict(prec=fde.P_TAU, dside=fde.D_LEFT,
+                                                                       shift=shift))]:
+        it, ms, conv = _first_step(fde, torch, p, dict(maxit=20000, **kw))
+        rows.append({"workload": "2D 1023^2 alpha=(1.7,1.4)", "preconditioner": name, "iters": it, "ms": ms,
+                     "converged": conv})
+        log(f"[table] {rows[-1]}")
+    return rows
+
+
+def table_paper2d(fi, fde, torch, np):
+    """Examples 2 and 3 (second-order weights, Crank-Nicolson, h_t = 1/n, n steps
+    to T = 1, with the source) on the GPU with P_F (tau.D, the tables' side),
+    FGMRES(30) to 1e-7, n = 2^k - 1 up to 1023: mean iterations per step,
+    time per step and the max-norm error against the exact solution at T = 1."""
+    rows = []
+    T = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda").reshape(-1).contiguous()
+    for example in (2, 3):
+        for n in (15, 31, 63, 127, 255, 511, 1023):
+            p = fi.paper_2d(n, example)
+            X, Y = p.meta["X"], p.meta["Y"]
+            a, b_ = p.alpha
+            S = T(fi.example23_source(X, Y, 0.0, a, b_))   # source = e^{-t} S
+            with fde.Plan(p, prec=fde.P_TAU, dside=fde.D_RIGHT, tol=p.tol) as plan:
+                u = T(p.u0)
+                b = torch.empty_like(u)
+                f = torch.empty_like(u)
+                its = []
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for m in range(1, n + 1):
+                    f.copy_(S).mul_(float(np.exp(-(m - 0.5) * p.dt)))
+                    plan.rhs(u, b, f=f)
+                    its.append(plan.solve(b, u).iters)   # x0 = u^{m-1}, solution in place
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                err = float(np.max(np.abs(u.cpu().numpy().reshape(X.shape) - fi.example23_exact(X, Y, n * p.dt))))
+            rows.append({"example": example, "n": n, "steps": n, "iters_mean": float(np.mean(its)),
+                         "iters_max": int(max(its)), "ms_per_step": 1e3 * dt / n, "max_error_T1": err})
+            log(f"[table] {rows[-1]}")
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -186,6 +271,9 @@ def main():
                     help="instances solved one plan at a time for the batched-vs-plan comparison")
     ap.add_argument("--only-batched", action="store_true",
                     help="run the batched leg alone (profiling); prints its JSON object")
+    ap.add_argument("--table", choices=["variants", "paper2d"], default=None,
+                    help="print a table instead of the benchmark line: preconditioner variants at the "
+                         "workload sizes, or the paper's 2D examples extended to n = 1023")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is a design "
@@ -203,6 +291,12 @@ def main():
     dev = torch.device("cuda:0")
     if args.only_batched:
         print(json.dumps({"batched": batched_leg(args, fi, fde, torch, np)}), flush=True)
+        return
+    if args.table == "variants":
+        print(json.dumps({"table": "variants", "rows": table_variants(fi, fde, torch, np)}), flush=True)
+        return
+    if args.table == "paper2d":
+        print(json.dumps({"table": "paper2d", "rows": table_paper2d(fi, fde, torch, np)}), flush=True)
         return
     prob = fi.variable_2d(n=args.n, steps=args.tsteps)
     N = prob.N

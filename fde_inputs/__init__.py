@@ -90,6 +90,50 @@ def separable_2d_coefficients(ax: float, ay: float, x: np.ndarray, y: np.ndarray
     return dp, dm, ep, em
 
 
+def example23_fields(n: int, alpha: float, beta: float):
+    """Coefficient fields of Examples 2 and 3 (Section 4) on (0,2)^2, (n, n)
+    arrays x fastest: d+ = G(3-a)(1+x)^a(1+y)^2, d- = G(3-a)(3-x)^a(3-y)^2,
+    e+ = G(3-b)(1+x)^2(1+y)^b, e- = G(3-b)(3-x)^2(3-y)^b."""
+    x, h = grid(n, 0.0, 2.0)
+    X, Y = np.meshgrid(x, x)
+    ca, cb = math.gamma(3.0 - alpha), math.gamma(3.0 - beta)
+    dp = ca * (1 + X) ** alpha * (1 + Y) ** 2
+    dm = ca * (3 - X) ** alpha * (3 - Y) ** 2
+    ep = cb * (1 + X) ** 2 * (1 + Y) ** beta
+    em = cb * (3 - X) ** 2 * (3 - Y) ** beta
+    return X, Y, dp, dm, ep, em
+
+
+def example23_exact(X, Y, t: float):
+    """Exact solution of Examples 2 and 3: 16 e^{-t} x^2 (2-x)^2 y^2 (2-y)^2."""
+    return 16.0 * math.exp(-t) * X ** 2 * (2 - X) ** 2 * Y ** 2 * (2 - Y) ** 2
+
+
+def _g23(gam, x, y):
+    return ((8 * x ** (2 - gam) - 24 * x ** (3 - gam) / (3 - gam)
+             + 24 * x ** (4 - gam) / ((4 - gam) * (3 - gam)))
+            * (1 + x) ** gam * (1 + y) ** 2 * y ** 2 * (2 - y) ** 2)
+
+
+def example23_source(X, Y, t: float, alpha: float, beta: float):
+    """Source term of Examples 2 and 3 (Section 4) at time t."""
+    return -16.0 * math.exp(-t) * (X ** 2 * (2 - X) ** 2 * Y ** 2 * (2 - Y) ** 2
+                                   + _g23(alpha, X, Y) + _g23(alpha, 2 - X, 2 - Y)
+                                   + _g23(beta, Y, X) + _g23(beta, 2 - Y, 2 - X))
+
+
+def paper_2d(n: int, example: int = 2, tol: float = 1e-7) -> Problem:
+    """Example 2 (alpha, beta = 1.8, 1.6) or Example 3 (1.8, 1.2): second-order
+    weights, Crank-Nicolson, h_t = 1/n, n steps to T = 1, u0 the exact
+    solution at t = 0 (the source is example23_source at t_{m-1/2})."""
+    alpha, beta = (1.8, 1.6) if example == 2 else (1.8, 1.2)
+    X, Y, dp, dm, ep, em = example23_fields(n, alpha, beta)
+    return Problem(dim=2, n=(n, n), alpha=(alpha, beta), lo=(0.0, 0.0), hi=(2.0, 2.0), dt=1.0 / n,
+                   dplus=dp, dminus=dm, eplus=ep, eminus=em, u0=example23_exact(X, Y, 0.0),
+                   steps=n, tol=tol, weights="weighted", time="cn", name=f"ex{example}-n{n}",
+                   meta={"X": X, "Y": Y})
+
+
 def uniform(rng, shape):
     return rng.uniform(-1.0, 1.0, size=shape)
 

@@ -76,3 +76,18 @@ def test_tau_apply_equals_dense_inverse(dside):
     tau = S @ np.diag(P.F.reshape(-1)) @ S
     Pm = D @ tau if dside == "left" else tau @ D
     np.testing.assert_allclose(Pinv @ Pm, np.eye(s.N), atol=1e-10)
+
+
+def test_example23_inputs_match_oracle_examples():
+    """The Example 2/3 problem data of fde_inputs (used by the GPU tables) are
+    the oracle's Example 2/3 fields, exact solution and source."""
+    import fde_inputs as fi
+    from oracle import examples as ex
+    for example, (a, b) in ((2, (1.8, 1.6)), (3, (1.8, 1.2))):
+        p = fi.paper_2d(15, example)
+        s, X, Y = ex.ex2_system(15, a, b)
+        assert np.allclose(p.dplus, s.dplus, rtol=0, atol=0) and np.array_equal(p.eminus, s.eminus)
+        assert np.array_equal(p.dminus, s.dminus) and np.array_equal(p.eplus, s.eplus)
+        assert p.dt == s.dt and p.time == s.time and p.weights == s.weights
+        assert np.array_equal(p.u0, ex.ex2_exact(X, Y, 0.0))
+        assert np.allclose(fi.example23_source(X, Y, 0.3, a, b), ex.ex2_source(X, Y, 0.3, a, b), rtol=1e-15)
