@@ -57,6 +57,7 @@ struct fde_plan_s {
   fde_params p;
   int dim = 1, n1 = 0, n2 = 1;
   long N = 0;
+  long ld = 0;   // leading dimension of the Krylov bases: N rounded up to 64 (aligned slots)
   double hx = 0, hy = 0, hxa = 0, nu = 0, kappa = 0, shift = 0;
   bool has_dinv = false;
   int dside = FDE_D_LEFT;
@@ -173,8 +174,8 @@ static size_t plan_bytes_impl(const fde_params* p) {
   b += (size_t)(n1 + n2 + 1) * (8 + 4);         // symbol samples
   b += (size_t)4 * (2 * (n1 + 1) + 2 * (n2 + 1)) * (16 + 8);  // twiddles and eigenvalues
   if (p->solver == FDE_S_PCG) b += (size_t)N * 8 * 6;
-  else b += (size_t)N * 8 * (2 * m + 1 + 3);
-  if (p->precision == FDE_MIXED) b += (size_t)N * 4 * (p->inner_steps + 1 + 6);
+  else b += (size_t)((N + 63) / 64 * 64) * 8 * (2 * m + 1) + (size_t)N * 8 * 3;
+  if (p->precision == FDE_MIXED) b += (size_t)((N + 63) / 64 * 64) * 4 * (p->inner_steps + 1) + (size_t)N * 4 * 6;
   b += (size_t)RED_MAXG * (KMAX + 1) * 8 + 2 * sizeof(KState);
   if (p->dim == 1 && n1 + 1 > 4096) b += (size_t)(n1 + 1) * (6 * 16 + (p->precision == FDE_MIXED ? 6 * 8 : 0) + 8 * 24);
   if (p->prec == FDE_P_TRI) b += (size_t)N * 6 * (8 + 4) + (size_t)TRI_PMAX * (7 * (8 + 4) + 4) + 4;
@@ -331,6 +332,7 @@ static fde_status assemble_impl(const fde_params* p, const double* dp, const dou
   pl->n1 = p->n[0];
   pl->n2 = p->dim == 2 ? p->n[1] : 1;
   pl->N = (long)pl->n1 * pl->n2;
+  pl->ld = (pl->N + 63) / 64 * 64;
   pl->hx = (p->hi[0] - p->lo[0]) / (pl->n1 + 1);
   pl->hxa = std::pow(pl->hx, p->alpha[0]);
   pl->nu = (p->time == FDE_T_EULER ? 1.0 : 2.0) * pl->hxa / p->dt;
@@ -506,13 +508,13 @@ static fde_status assemble_impl(const fde_params* p, const double* dp, const dou
   // workspace
   const int m = pl->m;
   const long nvec = p->solver == FDE_S_PCG ? 3 : (m + 1);
-  TRY(dalloc(pl, &pl->V, (size_t)nvec * N));
-  TRY(dalloc(pl, &pl->Z, (size_t)(p->solver == FDE_S_PCG ? 2 : m) * N));
+  TRY(dalloc(pl, &pl->V, (size_t)nvec * pl->ld));
+  TRY(dalloc(pl, &pl->Z, (size_t)(p->solver == FDE_S_PCG ? 2 : m) * pl->ld));
   TRY(dalloc(pl, &pl->t1, N));
   TRY(dalloc(pl, &pl->t2, N));
   TRY(dalloc(pl, &pl->t3, N));
   if (p->precision == FDE_MIXED) {
-    TRY(dalloc(pl, &pl->Vf, (size_t)(pl->kin + 1) * N));
+    TRY(dalloc(pl, &pl->Vf, (size_t)(pl->kin + 1) * pl->ld));
     TRY(dalloc(pl, &pl->t1f, N));
     TRY(dalloc(pl, &pl->t2f, N));
     TRY(dalloc(pl, &pl->t3f, N));
@@ -1101,13 +1103,14 @@ template <typename T, int KC, int EPI, int MODE>
 static void cgs_launch(fde_plan pl, const T* V, int k, T* w, KState* ks, int emode, int col, double* hstat,
                        hipStream_t st, const int* skip, const int* skip2) {
   const long N = pl->N;
+  // float32 kernels take element pairs: the same grid as float64 covers them in one pass
   const int G = red_grid(N, (long)RED_THREADS * EPI * 2);
   const int cls = sizeof(T) == 8 ? (MODE == CG_DOT ? FDE_PROBE_MDOT64 : FDE_PROBE_MAXPY64)
                                  : (MODE == CG_DOT ? FDE_PROBE_MDOT32 : FDE_PROBE_MAXPY32);
   const double bytes = (double)(k + (MODE == CG_DOT ? 1 : 2)) * N * sizeof(T);
   {
     ProbeScope ps(pl, cls, st, bytes, sizeof(T) == 8 ? FDE_PROBE_CGS64 : FDE_PROBE_CGS32);
-    hipLaunchKernelGGL((cgs_kernel<T, KC, EPI, MODE>), dim3(G), dim3(RED_THREADS), 0, st, V, N, k, w, w, N, emode,
+    hipLaunchKernelGGL((cgs_kernel<T, KC, EPI, MODE>), dim3(G), dim3(RED_THREADS), 0, st, V, pl->ld, k, w, w, N, emode,
                        col, pl->part, ks, hstat, skip, skip2);
   }
   if (MODE == CG_AXPY_NORM) finalize(pl, G, 1, ks, FK_NORM, emode, col, hstat, st, skip, skip2);
@@ -1148,9 +1151,10 @@ static void outer_step(fde_plan pl, int j, hipStream_t st) {
   const long N = pl->N;
   KState* ks = pl->ks;
   const int* skip = &ks->done;
-  double* vj = pl->V + (long)j * N;
-  double* w = pl->V + (long)(j + 1) * N;
-  double* zj = pl->Z + (long)j * N;
+  const long ld = pl->ld;
+  double* vj = pl->V + (long)j * ld;
+  double* w = pl->V + (long)(j + 1) * ld;
+  double* zj = pl->Z + (long)j * ld;
   if (pl->p.precision == FDE_FP64) {
     tau_matvec<double>(pl, vj, &ks->scale[j], zj, w, st, skip, nullptr);
   } else {
@@ -1165,14 +1169,14 @@ static void outer_step(fde_plan pl, int j, hipStream_t st) {
                          &ks->scale[j], skip, nullptr);
       norm_red<float>(pl, Vf, nullptr, nullptr, ki, EP_INNER0, st, skip, nullptr);
       for (int i = 0; i < pl->kin; ++i) {
-        float* vi = Vf + (long)i * N;
-        float* wi = Vf + (long)(i + 1) * N;
+        float* vi = Vf + (long)i * ld;
+        float* wi = Vf + (long)(i + 1) * ld;
         // inner kernels skip when the outer cycle is over or the inner one broke down
         tau_matvec<float>(pl, vi, &ki->scale[i], pl->zf, wi, st, s2, skip);
         cgs2_givens<float>(pl, Vf, wi, i, ki, nullptr, st, s2, skip);
       }
       hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(256), 0, st, ki, skip);
-      hipLaunchKernelGGL((update_kernel<float, float>), dim3(ew_grid(N)), dim3(RED_THREADS), 0, st, Vf, N,
+      hipLaunchKernelGGL((update_kernel<float, float>), dim3(ew_grid(N)), dim3(RED_THREADS), 0, st, Vf, ld,
                          (const float*)nullptr, pl->uf, N, ki, ki->scale, skip);
     }
     tau_only<float>(pl, pl->uf, nullptr, pl->zf, st, skip);
@@ -1185,7 +1189,7 @@ static void outer_step(fde_plan pl, int j, hipStream_t st) {
 
 // r = b - M x into basis slot 0 and its norm (cycle start / true residual).
 static void residual(fde_plan pl, const double* b, const double* x, hipStream_t st) {
-  double* tmp = pl->V + pl->N;   // slot 1 is free between cycles
+  double* tmp = pl->V + pl->ld;   // slot 1 is free between cycles
   matvec_only<double>(pl, x, tmp, pl->nu, 1.0, st, nullptr);
   norm_red<double>(pl, b, tmp, pl->V, pl->ks, EP_RESID, st);
 }
@@ -1219,7 +1223,7 @@ static fde_status solve_gmres(fde_plan pl, const double* b, double* x, fde_info*
       HIPCHK(hipEventRecord(pl->ev[j & 3], st));
     }
     hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(256), 0, st, ks, (const int*)nullptr);
-    hipLaunchKernelGGL((update_kernel<double, double>), dim3(ew_grid(N)), dim3(RED_THREADS), 0, st, pl->Z, N, x, x,
+    hipLaunchKernelGGL((update_kernel<double, double>), dim3(ew_grid(N)), dim3(RED_THREADS), 0, st, pl->Z, pl->ld, x, x,
                        N, ks, (const double*)nullptr, (const int*)nullptr);
     residual(pl, b, x, st);
     HIPCHK(hipGetLastError());
@@ -1256,8 +1260,8 @@ static fde_status solve_pcg(fde_plan pl, const double* b, double* x, fde_info* i
   KState* ks = pl->ks;
   const int* skip = &ks->done;
   double* r = pl->V;
-  double* p = pl->V + N;
-  double* q = pl->V + 2 * N;
+  double* p = pl->V + pl->ld;
+  double* q = pl->V + 2 * pl->ld;
   double* z = pl->Z;
   hipLaunchKernelGGL(ks_init_kernel, dim3(1), dim3(1), 0, st, ks, pl->p.maxit, 1, pl->p.tol);
   norm_red<double>(pl, b, nullptr, nullptr, ks, EP_BNORM, st);

@@ -270,6 +270,9 @@ __global__ void __launch_bounds__(RED_THREADS)
 cgs_kernel(const T* __restrict__ V, long ldv, int k, const T* w, T* out, long N, int emode, int col,
            double* part, KState* ks, double* hstat, const int* skip, const int* skip2) {
   if (skipped(skip, skip2)) return;
+  // float32 elements are taken in aligned pairs (8-byte loads, ldv even), so
+  // that every lane moves as many bytes per load as in the float64 kernel
+  constexpr int VW = sizeof(T) == 4 ? 2 : 1;
   constexpr int NA = MODE == CG_AXPY_NORM ? 1 : KC;
   __shared__ double red[16 * NA];
   __shared__ double tot[NA > KMAX + 1 ? NA : KMAX + 1];
@@ -282,36 +285,70 @@ cgs_kernel(const T* __restrict__ V, long ldv, int k, const T* w, T* out, long N,
   double acc[NA];
 #pragma unroll
   for (int q = 0; q < NA; ++q) acc[q] = 0.0;
+  const long nslot = (N + VW - 1) / VW;
   const long step = (long)gridDim.x * RED_THREADS * EPI;
-  for (long e0 = (long)blockIdx.x * RED_THREADS * EPI + threadIdx.x; e0 < N; e0 += step) {
-    T vq[EPI][KC];
-    double x[EPI];
-    bool ok[EPI];
+  for (long s0 = (long)blockIdx.x * RED_THREADS * EPI + threadIdx.x; s0 < nslot; s0 += step) {
+    T vq[EPI][KC][VW];
+    double x[EPI][VW];
+    bool ok[EPI][VW];
 #pragma unroll
     for (int i = 0; i < EPI; ++i) {
-      const long e = e0 + (long)i * RED_THREADS;
-      ok[i] = e < N;
-      x[i] = ok[i] ? (double)w[e] : 0.0;
+      const long e = (s0 + (long)i * RED_THREADS) * VW;
+      const bool full = e + VW <= N;
 #pragma unroll
-      for (int q = 0; q < KC; ++q) vq[i][q] = (ok[i] && q < k) ? V[(long)q * ldv + e] : T(0);
+      for (int v = 0; v < VW; ++v) ok[i][v] = e + v < N;
+      if constexpr (VW == 2) {
+        if (full) {
+          const float2 wv = *reinterpret_cast<const float2*>(w + e);
+          x[i][0] = wv.x;
+          x[i][1] = wv.y;
+#pragma unroll
+          for (int q = 0; q < KC; ++q) {
+            float2 vv = make_float2(0.0f, 0.0f);
+            if (q < k) vv = *reinterpret_cast<const float2*>(V + (long)q * ldv + e);
+            vq[i][q][0] = vv.x;
+            vq[i][q][1] = vv.y;
+          }
+          continue;
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < VW; ++v) {
+        x[i][v] = ok[i][v] ? (double)w[e + v] : 0.0;
+#pragma unroll
+        for (int q = 0; q < KC; ++q) vq[i][q][v] = (ok[i][v] && q < k) ? V[(long)q * ldv + e + v] : T(0);
+      }
     }
     if (MODE != CG_DOT) {
 #pragma unroll
       for (int i = 0; i < EPI; ++i) {
+        T r[VW];
 #pragma unroll
-        for (int q = 0; q < KC; ++q) x[i] -= coef[q] * (double)vq[i][q];
-        const T r = (T)x[i];
-        if (ok[i]) out[e0 + (long)i * RED_THREADS] = r;
-        x[i] = (double)r;
+        for (int v = 0; v < VW; ++v) {
+#pragma unroll
+          for (int q = 0; q < KC; ++q) x[i][v] -= coef[q] * (double)vq[i][q][v];
+          r[v] = (T)x[i][v];
+          x[i][v] = (double)r[v];
+        }
+        const long e = (s0 + (long)i * RED_THREADS) * VW;
+        if constexpr (VW == 2) {
+          if (ok[i][1]) *reinterpret_cast<float2*>(out + e) = make_float2(r[0], r[1]);
+          else if (ok[i][0]) out[e] = r[0];
+        } else {
+          if (ok[i][0]) out[e] = r[0];
+        }
       }
     }
 #pragma unroll
     for (int i = 0; i < EPI; ++i) {
-      if (MODE == CG_AXPY_NORM) {
-        acc[0] += x[i] * x[i];
-      } else {
 #pragma unroll
-        for (int q = 0; q < KC; ++q) acc[q] += (double)vq[i][q] * x[i];
+      for (int v = 0; v < VW; ++v) {
+        if (MODE == CG_AXPY_NORM) {
+          acc[0] += x[i][v] * x[i][v];
+        } else {
+#pragma unroll
+          for (int q = 0; q < KC; ++q) acc[q] += (double)vq[i][q][v] * x[i][v];
+        }
       }
     }
   }
