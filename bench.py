@@ -264,7 +264,7 @@ def main():
     ap.add_argument("--probe-class", default="line32_dst_storez_toeplitz")
     ap.add_argument("--serve-rate", type=float, default=500.0, help="Poisson arrival rate of the served leg")
     ap.add_argument("--serve-count", type=int, default=32, help="requests in the served leg (0: skip)")
-    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--batch-count", type=int, default=512, help="instances of the batched leg (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=2, help="timed time steps of the batched leg")
     ap.add_argument("--batch-plan-sample", type=int, default=64,
@@ -388,13 +388,13 @@ def main():
     served = None
     if args.serve_count > 0:
         from paper_1912_13304_amd import serve
-        arr = fi.served_stream(args.serve_rate, args.serve_count, seed=5, n1d=(1023, 4095))
+        arr = fi.served_stream(args.serve_rate, args.serve_count, seed=5, n1d=(1023, 65535))
         serve.serve_stream(arr[:4], slots=args.serve_slots, precision=fde.MIXED, inner_steps=args.inner)  # warm
         res, wall = serve.serve_stream(arr, slots=args.serve_slots, precision=fde.MIXED, inner_steps=args.inner)
         served = serve.latency_stats(res)
         served.update(rate_req_per_s=args.serve_rate, slots=args.serve_slots,
-                      mix="70% 1D n in [1023, 4095] (2^k-1), 30% 2D n in {127,255,511,1023}; 5-50 steps; "
-                          "alpha ~ U(1.1,1.9); mixed precision, tol 1e-8")
+                      mix="70% 1D n log-uniform in [1023, 65535] rounded to 2^k-1, 30% 2D n in "
+                          "{127,255,511,1023}; 5-50 steps; alpha ~ U(1.1,1.9); mixed precision, tol 1e-8")
         log(f"[bench] served: {served}")
 
     batched = batched_leg(args, fi, fde, torch, np) if args.batch_count > 0 else None
