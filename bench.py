@@ -267,7 +267,7 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--batch-count", type=int, default=512, help="instances of the batched leg (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=2, help="timed time steps of the batched leg")
-    ap.add_argument("--batch-plan-sample", type=int, default=64,
+    ap.add_argument("--batch-plan-sample", type=int, default=512,
                     help="instances solved one plan at a time for the batched-vs-plan comparison")
     ap.add_argument("--only-batched", action="store_true",
                     help="run the batched leg alone (profiling); prints its JSON object")
