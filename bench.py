@@ -249,6 +249,49 @@ def table_paper2d(fi, fde, torch, np):
     return rows
 
 
+def one_d_legs(args, fi, fde, torch, np):
+    """The 1D workloads: (a) the constant-coefficient system (d+ = d- = 1,
+    n = 1023, alpha = 1.5) solved by PCG with the Case I preconditioner to
+    1e-10, time-to-tol per solve; (b) 20 implicit steps of the 1D
+    variable-coefficient problem at n = 65535 for alpha = 1.2, 1.5, 1.8,
+    float64 and mixed forms, solves per second."""
+    T = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda").reshape(-1).contiguous()
+    out = {}
+    p = fi.constant_1d()
+    with fde.Plan(p) as plan:
+        b = T(p.b)
+        times, info = [], None
+        for _ in range(20):
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = plan.solve(b, x)
+            times.append(time.perf_counter() - t0)
+    out["pcg_constant_1023"] = {"time_to_tol_us_min": 1e6 * min(times), "time_to_tol_us_median": 1e6 * float(np.median(times)),
+                                "iters": info.iters, "relres": info.relres_true, "converged": bool(info.converged)}
+    log(f"[bench] 1D PCG: {out['pcg_constant_1023']}")
+    jobs = {}
+    for alpha in (1.2, 1.5, 1.8):
+        p = fi.variable_1d(n=65535, alpha=alpha, steps=20)
+        for name, kw in (("fp64", dict(precision=fde.FP64)), ("mixed", dict(precision=fde.MIXED, inner_steps=args.inner))):
+            with fde.Plan(p, **kw) as plan:
+                u = T(p.u0)
+                bb = torch.empty_like(u)
+                its = []
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(p.steps):
+                    plan.rhs(u, bb)
+                    its.append(plan.solve(bb, u).iters)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+            jobs[f"alpha={alpha} {name}"] = {"solves_per_s": p.steps / dt, "ms_per_solve": 1e3 * dt / p.steps,
+                                             "iters_mean": float(np.mean(its))}
+            log(f"[bench] 1D job alpha={alpha} {name}: {jobs[f'alpha={alpha} {name}']}")
+    out["variable_65535_20_steps"] = jobs
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -263,6 +306,10 @@ def main():
                     help="skip the per-class sampling pass; probe --probe-class in the timed region")
     ap.add_argument("--probe-class", default="line32_dst_storez_toeplitz")
     ap.add_argument("--serve-rate", type=float, default=500.0, help="Poisson arrival rate of the served leg")
+    ap.add_argument("--serve-sweep", default="50,2000",
+                    help="further arrival rates of the served leg, reported in served_sweep ('' to skip)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 1D legs (constant-coefficient PCG time-to-tol, 1D 20-step jobs)")
     ap.add_argument("--serve-count", type=int, default=32, help="requests in the served leg (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--batch-count", type=int, default=512, help="instances of the batched leg (0: skip)")
@@ -396,8 +443,18 @@ def main():
                       mix="70% 1D n log-uniform in [1023, 65535] rounded to 2^k-1, 30% 2D n in "
                           "{127,255,511,1023}; 5-50 steps; alpha ~ U(1.1,1.9); mixed precision, tol 1e-8")
         log(f"[bench] served: {served}")
+        sweep = []
+        for r in [float(x) for x in args.serve_sweep.split(",") if x.strip()]:
+            arr = fi.served_stream(r, args.serve_count, seed=5, n1d=(1023, 65535))
+            res, wall = serve.serve_stream(arr, slots=args.serve_slots, precision=fde.MIXED, inner_steps=args.inner)
+            st = serve.latency_stats(res)
+            st.update(rate_req_per_s=r)
+            sweep.append(st)
+            log(f"[bench] served at {r}/s: {st}")
+        served["sweep"] = sweep
 
     batched = batched_leg(args, fi, fde, torch, np) if args.batch_count > 0 else None
+    legs_1d = None if args.no_configs else one_d_legs(args, fi, fde, torch, np)
 
     # plain copy bandwidth on the same GPU (1 GiB read + 1 GiB write)
     src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
@@ -469,6 +526,7 @@ def main():
                      "copy_GBps": copy_gbs},
         "served": served,
         "batched": batched,
+        "one_d": legs_1d,
         "p99_served_latency_ms": served["p99_ms"] if served else None,
         "cpu_baseline": cpu,
         "parity": parity,
