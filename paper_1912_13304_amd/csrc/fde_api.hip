@@ -1145,6 +1145,29 @@ static fde_status read_header(fde_plan pl, KState* ks, hipStream_t st) {
   return FDE_OK;
 }
 
+// The float32 inner solve of one outer step of the mixed form: GMRES(kin)
+// from x = 0 on the float32 copy of v_j (basis slot 0 of Vf), then
+// zf = P^{-1} uf.  Every kernel skips when the outer cycle is over; the inner
+// ones also when the inner cycle broke down.
+static void inner_solve(fde_plan pl, hipStream_t st) {
+  const long N = pl->N, ld = pl->ld;
+  const int* skip = &pl->ks->done;
+  KState* ki = pl->ksi;
+  const int* s2 = &ki->done;
+  float* Vf = pl->Vf;
+  norm_red<float>(pl, Vf, nullptr, nullptr, ki, EP_INNER0, st, skip, nullptr);
+  for (int i = 0; i < pl->kin; ++i) {
+    float* vi = Vf + (long)i * ld;
+    float* wi = Vf + (long)(i + 1) * ld;
+    tau_matvec<float>(pl, vi, &ki->scale[i], pl->zf, wi, st, s2, skip);
+    cgs2_givens<float>(pl, Vf, wi, i, ki, nullptr, st, s2, skip);
+  }
+  hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(256), 0, st, ki, skip);
+  hipLaunchKernelGGL((update_kernel<float, float>), dim3(ew_grid(N)), dim3(RED_THREADS), 0, st, Vf, ld,
+                     (const float*)nullptr, pl->uf, N, ki, ki->scale, skip);
+  tau_only<float>(pl, pl->uf, nullptr, pl->zf, st, skip);
+}
+
 // One outer Arnoldi step j: z_j = P^{-1} v_j (FP64, or the float32 inner
 // solve), w = M z_j into basis slot j+1, CGS2, Givens.
 static void outer_step(fde_plan pl, int j, hipStream_t st) {
@@ -1158,28 +1181,15 @@ static void outer_step(fde_plan pl, int j, hipStream_t st) {
   if (pl->p.precision == FDE_FP64) {
     tau_matvec<double>(pl, vj, &ks->scale[j], zj, w, st, skip, nullptr);
   } else {
-    KState* ki = pl->ksi;
-    const int* s2 = &ki->done;
     if (pl->kin == 0) {
       hipLaunchKernelGGL((scale_cast_kernel<double, float>), dim3(ew_grid(N)), dim3(256), 0, st, vj, pl->uf, N,
                          &ks->scale[j], skip, nullptr);
+      tau_only<float>(pl, pl->uf, nullptr, pl->zf, st, skip);
     } else {
-      float* Vf = pl->Vf;
-      hipLaunchKernelGGL((scale_cast_kernel<double, float>), dim3(ew_grid(N)), dim3(256), 0, st, vj, Vf, N,
+      hipLaunchKernelGGL((scale_cast_kernel<double, float>), dim3(ew_grid(N)), dim3(256), 0, st, vj, pl->Vf, N,
                          &ks->scale[j], skip, nullptr);
-      norm_red<float>(pl, Vf, nullptr, nullptr, ki, EP_INNER0, st, skip, nullptr);
-      for (int i = 0; i < pl->kin; ++i) {
-        float* vi = Vf + (long)i * ld;
-        float* wi = Vf + (long)(i + 1) * ld;
-        // inner kernels skip when the outer cycle is over or the inner one broke down
-        tau_matvec<float>(pl, vi, &ki->scale[i], pl->zf, wi, st, s2, skip);
-        cgs2_givens<float>(pl, Vf, wi, i, ki, nullptr, st, s2, skip);
-      }
-      hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(256), 0, st, ki, skip);
-      hipLaunchKernelGGL((update_kernel<float, float>), dim3(ew_grid(N)), dim3(RED_THREADS), 0, st, Vf, ld,
-                         (const float*)nullptr, pl->uf, N, ki, ki->scale, skip);
+      inner_solve(pl, st);
     }
-    tau_only<float>(pl, pl->uf, nullptr, pl->zf, st, skip);
     hipLaunchKernelGGL((scale_cast_kernel<float, double>), dim3(ew_grid(N)), dim3(256), 0, st, pl->zf, zj, N,
                        nullptr, skip, nullptr);
     matvec_only<double>(pl, zj, w, pl->nu, 1.0, st, skip);

@@ -50,6 +50,25 @@ def test_1d_operator_and_structure():
     np.testing.assert_allclose(sup, np.diag(A, 1), rtol=1e-14)
 
 
+@pytest.mark.parametrize("dim", [1, 2])
+def test_first_order_rows_dominant_by_nu(dim):
+    """Every row of the first-order (shifted Grunwald) M has diagonal minus
+    off-diagonal absolute sum >= nu, so ||M^{-1}||_inf <= 1/nu (Varah); the
+    mixed-form GPU tests bound the distance between two tol-accurate
+    solutions with it."""
+    if dim == 1:
+        p = fi.variable_1d(n=60, alpha=1.3, seed=4)
+    else:
+        p = fi.variable_2d(n=9, n2=7, ax=1.9, ay=1.1, seed=4)
+    s = FDESystem.from_problem(p)
+    assert s.weights == "shifted"
+    A = s.dense()
+    d = np.diag(A)
+    margin = d - (np.abs(A).sum(axis=1) - np.abs(d))
+    assert margin.min() >= s.nu * (1 - 1e-12)
+    assert np.abs(np.linalg.inv(A)).sum(axis=1).max() <= (1 + 1e-12) / s.nu
+
+
 def test_constant_case_is_spd_and_hat_equals_shifted_tau():
     p = fi.constant_1d(n=31)
     s = FDESystem.from_problem(p)
