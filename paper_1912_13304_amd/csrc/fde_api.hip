@@ -40,6 +40,7 @@ extern "C" const char* fde_last_error(void) { return fde::g_err.c_str(); }
 struct Dir {
   int n = 0, P = 0, logP = 0, nlines = 0, B = 1, logB = 0;
   long ls = 0, es = 0;
+  bool cols = false;   // lines are columns of a row-major array (line_kernel<.., COLS = true, ..>)
 };
 
 template <typename T>
@@ -64,6 +65,8 @@ struct fde_plan_s {
   TriDev<double> tri64;   // P_tri factors and work (FDE_P_TRI)
   TriDev<float> tri32;
   Dir rows, trows;   // lines along x (rows of the (n2, n1) array); along y (rows of its transpose)
+  Dir ycols;         // lines along y read in place (columns of the (n2, n1) array)
+  bool use_cols = false;   // y-direction passes on ycols (no transposes)
   bool big = false;  // 1D line longer than one workgroup: four-step FFT over kernels
   int P1 = 0, P2 = 0, log1 = 0, log2 = 0;
   Consts<double> c64;
@@ -98,7 +101,7 @@ template <> float* fde_plan_s::tmp<float>(int i) { return i == 1 ? t1f : i == 2 
 // workgroups share a CU, so that the load, transform and store phases of
 // different lines overlap.
 static void choose_tile(Dir& d) {
-  int B = std::max(1, 512 / d.P);
+  const int B = d.cols ? cols_per_tile(d.P) : rows_per_tile(d.P);
   d.B = B;
   d.logB = ilog2(B);
 }
@@ -361,6 +364,14 @@ static fde_status assemble_impl(const fde_params* p, const double* dp, const dou
     pl->trows.ls = pl->n2;
     pl->trows.es = 1;
     choose_tile(pl->trows);
+    pl->ycols = pl->trows;
+    pl->ycols.ls = 1;
+    pl->ycols.es = pl->n1;
+    pl->ycols.cols = true;
+    choose_tile(pl->ycols);
+    // with one column per tile every global access would be a lone element:
+    // such sizes keep the transposes
+    pl->use_cols = pl->ycols.B >= 2;
   }
 
   // coefficients: validate and copy
@@ -628,18 +639,20 @@ struct ProbePlanScope {
   ~ProbePlanScope() { g_probe_plan = nullptr; }
 };
 
-template <typename T, int FL, int LOGP>
+template <typename T, bool COLS, int FL, int LOGP>
 static void launch_line_k(const Dir& d, const LineArgs<T>& a, int grid, int nth, size_t lds, hipStream_t st) {
   static bool attr_set = false;
   if (!attr_set) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&line_kernel<T, false, FL, LOGP>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&line_kernel<T, COLS, FL, LOGP>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set = true;
   }
-  hipLaunchKernelGGL((line_kernel<T, false, FL, LOGP>), dim3(grid), dim3(nth), lds, st, a);
+  hipLaunchKernelGGL((line_kernel<T, COLS, FL, LOGP>), dim3(grid), dim3(nth), lds, st, a);
 }
 
-template <typename T, int FL>
+// COLS = true: d is a column direction (d.cols); only the y-direction
+// programs are instantiated in that form.
+template <typename T, int FL, bool COLS = false>
 static void launch_line(const Dir& d, LineArgs<T> a, hipStream_t st) {
   a.n = d.n;
   a.P = d.P;
@@ -660,18 +673,33 @@ static void launch_line(const Dir& d, LineArgs<T> a, hipStream_t st) {
   const double bytes = (double)nvec * (double)d.n * (double)d.nlines * sizeof(T);
   ProbeScope ps(g_probe_plan, sizeof(T) == 8 ? FDE_PROBE_LINE64 : FDE_PROBE_LINE32, st, bytes,
                 (sizeof(T) == 8 ? FDE_PROBE_LINE64_VARIANT : FDE_PROBE_LINE32_VARIANT) + FL);
-  switch (d.logP) {
-    case 3: launch_line_k<T, FL, 3>(d, a, grid, nth, lds, st); break;
-    case 4: launch_line_k<T, FL, 4>(d, a, grid, nth, lds, st); break;
-    case 5: launch_line_k<T, FL, 5>(d, a, grid, nth, lds, st); break;
-    case 6: launch_line_k<T, FL, 6>(d, a, grid, nth, lds, st); break;
-    case 7: launch_line_k<T, FL, 7>(d, a, grid, nth, lds, st); break;
-    case 8: launch_line_k<T, FL, 8>(d, a, grid, nth, lds, st); break;
-    case 9: launch_line_k<T, FL, 9>(d, a, grid, nth, lds, st); break;
-    case 10: launch_line_k<T, FL, 10>(d, a, grid, nth, lds, st); break;
-    case 11: launch_line_k<T, FL, 11>(d, a, grid, nth, lds, st); break;
-    case 12: launch_line_k<T, FL, 12>(d, a, grid, nth, lds, st); break;
-    default: launch_line_k<T, FL, 0>(d, a, grid, nth, lds, st); break;
+  if constexpr (COLS) {
+    switch (d.logP) {   // cols_per_tile(P) >= 2: P <= 2048
+      case 3: launch_line_k<T, true, FL, 3>(d, a, grid, nth, lds, st); break;
+      case 4: launch_line_k<T, true, FL, 4>(d, a, grid, nth, lds, st); break;
+      case 5: launch_line_k<T, true, FL, 5>(d, a, grid, nth, lds, st); break;
+      case 6: launch_line_k<T, true, FL, 6>(d, a, grid, nth, lds, st); break;
+      case 7: launch_line_k<T, true, FL, 7>(d, a, grid, nth, lds, st); break;
+      case 8: launch_line_k<T, true, FL, 8>(d, a, grid, nth, lds, st); break;
+      case 9: launch_line_k<T, true, FL, 9>(d, a, grid, nth, lds, st); break;
+      case 10: launch_line_k<T, true, FL, 10>(d, a, grid, nth, lds, st); break;
+      case 11: launch_line_k<T, true, FL, 11>(d, a, grid, nth, lds, st); break;
+      default: launch_line_k<T, true, FL, 0>(d, a, grid, nth, lds, st); break;
+    }
+  } else {
+    switch (d.logP) {
+      case 3: launch_line_k<T, false, FL, 3>(d, a, grid, nth, lds, st); break;
+      case 4: launch_line_k<T, false, FL, 4>(d, a, grid, nth, lds, st); break;
+      case 5: launch_line_k<T, false, FL, 5>(d, a, grid, nth, lds, st); break;
+      case 6: launch_line_k<T, false, FL, 6>(d, a, grid, nth, lds, st); break;
+      case 7: launch_line_k<T, false, FL, 7>(d, a, grid, nth, lds, st); break;
+      case 8: launch_line_k<T, false, FL, 8>(d, a, grid, nth, lds, st); break;
+      case 9: launch_line_k<T, false, FL, 9>(d, a, grid, nth, lds, st); break;
+      case 10: launch_line_k<T, false, FL, 10>(d, a, grid, nth, lds, st); break;
+      case 11: launch_line_k<T, false, FL, 11>(d, a, grid, nth, lds, st); break;
+      case 12: launch_line_k<T, false, FL, 12>(d, a, grid, nth, lds, st); break;
+      default: launch_line_k<T, false, FL, 0>(d, a, grid, nth, lds, st); break;
+    }
   }
 }
 
@@ -692,8 +720,8 @@ static LineArgs<T> toep_args(fde_plan pl, bool ydir, const int* skip, const int*
   LineArgs<T> a{};
   a.W2 = ydir ? c.W2y : c.W2x;
   a.lam = ydir ? c.lamy : c.lamx;
-  a.cplus = ydir ? c.ept : c.dp;
-  a.cminus = ydir ? c.emt : c.dm;
+  a.cplus = ydir ? (pl->use_cols ? c.ep : c.ept) : c.dp;
+  a.cminus = ydir ? (pl->use_cols ? c.em : c.emt) : c.dm;
   a.skip = skip;
   a.skip2 = skip2;
   return a;
@@ -715,6 +743,17 @@ static void transpose(fde_plan pl, const T* in, T* out, int rows, int cols, cons
 template <typename T>
 static void add_y_part(fde_plan pl, const T* x, const T* xpart, T* y, T tscale, hipStream_t st, const int* skip,
                        const int* skip2) {
+  if (pl->use_cols) {
+    LineArgs<T> q = toep_args<T>(pl, true, skip, skip2);
+    q.in = x;
+    q.base = xpart;
+    q.bscale = xpart ? T(1) : T(0);
+    q.tscale = tscale * (T)pl->kappa;
+    q.out = y;
+    if (xpart) launch_line<T, LF_TOEP | LF_EXTBASE, true>(pl->ycols, q, st);
+    else launch_line<T, LF_TOEP, true>(pl->ycols, q, st);
+    return;
+  }
   T* xt = pl->tmp<T>(1);
   T* yt = pl->tmp<T>(2);
   transpose<T>(pl, x, xt, pl->n2, pl->n1, nullptr, st, skip, skip2);
@@ -836,6 +875,31 @@ static void tri_apply(fde_plan pl, const T* v, const double* sc, T* z, hipStream
   hipLaunchKernelGGL((tri_back_kernel<T, T>), dim3(ew_grid(pl->N)), dim3(256), 0, st, t, pl->N, z, skip, skip2);
 }
 
+// 2D: out = (S (x) I) F^{-1} (S (x) I) applied along y to t (the middle of
+// P^{-1}: DST along y, division by F_N, DST along y), in place on the
+// columns, or on the transpose (t is overwritten then).
+template <typename T>
+static void y_dst_f_dst(fde_plan pl, T* t, T* out, hipStream_t st, const int* skip, const int* skip2) {
+  const Consts<T>& c = consts<T>(pl);
+  LineArgs<T> b{};
+  b.fline = c.fx;
+  b.felem = c.fy;
+  b.W2 = c.W2y;
+  b.skip = skip;
+  b.skip2 = skip2;
+  if (pl->use_cols) {
+    b.in = t;
+    b.out = out;
+    launch_line<T, LF_DST1 | LF_FDST2, true>(pl->ycols, b, st);
+    return;
+  }
+  transpose<T>(pl, t, out, pl->n2, pl->n1, nullptr, st, skip, skip2);
+  b.in = out;
+  b.out = t;
+  launch_line<T, LF_DST1 | LF_FDST2>(pl->trows, b, st);
+  transpose<T>(pl, t, out, pl->n1, pl->n2, nullptr, st, skip, skip2);
+}
+
 template <typename T>
 static void matvec_only(fde_plan pl, const T* x, T* y, T bscale, T tscale, hipStream_t st, const int* skip,
                         const int* skip2 = nullptr);
@@ -899,18 +963,8 @@ static void tau_matvec(fde_plan pl, const T* v, const double* sc, T* z, T* w, hi
     a.skip = skip;
     a.skip2 = skip2;
     launch_line<T, LF_DST1>(pl->rows, a, st);
-    // along y on the transpose: DST, divide by F, DST
-    transpose<T>(pl, t1, t2, pl->n2, pl->n1, nullptr, st, skip, skip2);
-    LineArgs<T> b{};
-    b.in = t2;
-    b.fline = c.fx;
-    b.felem = c.fy;
-    b.W2 = c.W2y;
-    b.out = t1;
-    b.skip = skip;
-    b.skip2 = skip2;
-    launch_line<T, LF_DST1 | LF_FDST2>(pl->trows, b, st);
-    transpose<T>(pl, t1, t2, pl->n1, pl->n2, nullptr, st, skip, skip2);
+    // along y: DST, divide by F, DST
+    y_dst_f_dst<T>(pl, t1, t2, st, skip, skip2);
     // rows: DST along x (D^{-1} after for tau D), store z, x-direction Toeplitz
     LineArgs<T> r = toep_args<T>(pl, false, skip, skip2);
     r.in = t2;
@@ -979,17 +1033,7 @@ static void tau_only(fde_plan pl, const T* v, const double* sc, T* z, hipStream_
   a.skip = skip;
   a.skip2 = skip2;
   launch_line<T, LF_DST1>(pl->rows, a, st);
-  transpose<T>(pl, t1, t2, pl->n2, pl->n1, nullptr, st, skip, skip2);
-  LineArgs<T> b{};
-  b.in = t2;
-  b.fline = c.fx;
-  b.felem = c.fy;
-  b.W2 = c.W2y;
-  b.out = t1;
-  b.skip = skip;
-  b.skip2 = skip2;
-  launch_line<T, LF_DST1 | LF_FDST2>(pl->trows, b, st);
-  transpose<T>(pl, t1, t2, pl->n1, pl->n2, nullptr, st, skip, skip2);
+  y_dst_f_dst<T>(pl, t1, t2, st, skip, skip2);
   LineArgs<T> r{};
   r.in = t2;
   r.post = post;

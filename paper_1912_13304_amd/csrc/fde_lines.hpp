@@ -111,6 +111,13 @@ __device__ __forceinline__ void dftR(cx<T>* v) {
 __device__ __forceinline__ int pidx(int i) { return i; }
 __host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v >> 1); }
 __host__ __device__ constexpr int line_stride(int P) { return P + 1; }
+// Lines per workgroup: rows (contiguous lines) fill one wavefront at least;
+// columns (lines of stride n1) take up to four neighbouring columns, so that
+// every row of the tile is one 16- or 32-byte segment, within 512 threads.
+__host__ __device__ constexpr int rows_per_tile(int P) { return P >= 512 ? 1 : 512 / P; }
+__host__ __device__ constexpr int cols_per_tile(int P) {
+  return rows_per_tile(P) > (4096 / P < 4 ? 4096 / P : 4) ? rows_per_tile(P) : (4096 / P < 4 ? 4096 / P : 4);
+}
 
 // One Stockham pass of radix R over B lines of length P in LDS (line stride
 // LS complex elements).  Ls = product of the radices of earlier passes.
@@ -236,9 +243,13 @@ __device__ __forceinline__ int xcd_tile(int ntiles) {
   return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
 }
 
-// LOGP > 0: transform size fixed at compile time (P = 2^LOGP, B = max(1,
-// 512/P) lines per workgroup), so that pass radices, strides, twiddle
-// indices and LDS offsets are constants; LOGP = 0 reads them from `a`.
+// LOGP > 0: transform size fixed at compile time (P = 2^LOGP, B =
+// rows_per_tile(P) or cols_per_tile(P) lines per workgroup), so that pass
+// radices, strides, twiddle indices and LDS offsets are constants; LOGP = 0
+// reads them from `a`.  COLS: the B lines of a tile are neighbouring columns
+// (line stride 1, element stride n1), and consecutive threads take the B
+// entries of one row, so that the global accesses of a wavefront are row
+// segments rather than single elements.
 template <typename T, bool COLS, int FL, int LOGP>
 __global__ void __launch_bounds__(512) line_kernel(LineArgs<T> a) {
   constexpr int EPT = 8;
@@ -249,7 +260,7 @@ __global__ void __launch_bounds__(512) line_kernel(LineArgs<T> a) {
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
 
   constexpr int CP = LOGP > 0 ? (1 << LOGP) : 0;
-  constexpr int CB = LOGP > 0 ? (CP >= 512 ? 1 : 512 / CP) : 0;
+  constexpr int CB = LOGP > 0 ? (COLS ? cols_per_tile(CP) : rows_per_tile(CP)) : 0;
   const int logP = LOGP > 0 ? LOGP : a.logP;
   const int P = LOGP > 0 ? CP : a.P;
   const int B = LOGP > 0 ? CB : a.B;

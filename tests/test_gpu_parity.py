@@ -15,7 +15,7 @@ from oracle.system import FDESystem
 pytestmark = pytest.mark.gpu
 
 SHAPES_1D = [1, 3, 7, 15, 63, 255, 1023, 4095]
-SHAPES_2D = [(7, 3), (15, 31), (63, 63), (127, 255), (255, 127)]
+SHAPES_2D = [(7, 3), (15, 31), (63, 63), (127, 255), (255, 127), (3, 1023), (15, 4095)]
 
 
 def prob1d(n, alpha=1.37, weights="shifted", time="euler", seed=11):
