@@ -1171,6 +1171,17 @@ static void cgs_pass(fde_plan pl, const T* V, int k, T* w, KState* ks, int emode
   else cgs_launch<T, 32, 1 * X, MODE>(pl, V, k, w, ks, emode, col, hstat, st, skip, skip2);
 }
 
+// One classical Gram-Schmidt pass (h = V^T w into h2, then w -= V h and
+// ||w|| in one pass) and the Givens column j; h1 stays zero from the cycle
+// start.
+template <typename T>
+static void cgs1_givens(fde_plan pl, const T* V, T* w, int j, KState* ks, double* hstat, hipStream_t st,
+                        const int* skip, const int* skip2) {
+  const int k = j + 1;
+  cgs_pass<T, CG_DOT>(pl, V, k, w, ks, EP_H2, j, nullptr, st, skip, skip2);
+  cgs_pass<T, CG_AXPY_NORM>(pl, V, k, w, ks, EP_GIVENS, j, hstat, st, skip, skip2);
+}
+
 // CGS2 of w (= basis slot j+1) against basis vectors 0..j, then the Givens
 // column j: h1 = V^T w; w -= V h1 and h2 = V^T w in one pass; w -= V h2 and
 // ||w|| in one pass.
@@ -1192,7 +1203,10 @@ static fde_status read_header(fde_plan pl, KState* ks, hipStream_t st) {
 // The float32 inner solve of one outer step of the mixed form: GMRES(kin)
 // from x = 0 on the float32 copy of v_j (basis slot 0 of Vf), then
 // zf = P^{-1} uf.  Every kernel skips when the outer cycle is over; the inner
-// ones also when the inner cycle broke down.
+// ones also when the inner cycle broke down.  The inner basis is
+// orthogonalised with one classical Gram-Schmidt pass: the inner solve only
+// shapes the flexible preconditioner, while the float64 outer cycle (CGS2)
+// and its true-residual test decide the answer.
 static void inner_solve(fde_plan pl, hipStream_t st) {
   const long N = pl->N, ld = pl->ld;
   const int* skip = &pl->ks->done;
@@ -1204,7 +1218,7 @@ static void inner_solve(fde_plan pl, hipStream_t st) {
     float* vi = Vf + (long)i * ld;
     float* wi = Vf + (long)(i + 1) * ld;
     tau_matvec<float>(pl, vi, &ki->scale[i], pl->zf, wi, st, s2, skip);
-    cgs2_givens<float>(pl, Vf, wi, i, ki, nullptr, st, s2, skip);
+    cgs1_givens<float>(pl, Vf, wi, i, ki, nullptr, st, s2, skip);
   }
   hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(256), 0, st, ki, skip);
   hipLaunchKernelGGL((update_kernel<float, float>), dim3(ew_grid(N)), dim3(RED_THREADS), 0, st, Vf, ld,

@@ -168,6 +168,7 @@ __device__ inline void epilogue_norm(KState* ks, int mode, int col, double ss, d
     ks->beta = nrm;
     ks->kdone = 0;
     ks->breakdown = 0;
+    for (int i = 0; i <= KMAX; ++i) ks->h1[i] = 0.0;   // single-pass Gram-Schmidt fills h2 only
     ks->done = !(nrm > 0.0) || !isfinite(nrm);
     ks->g[0] = nrm;
     for (int i = 1; i <= KMAX; ++i) ks->g[i] = 0.0;
