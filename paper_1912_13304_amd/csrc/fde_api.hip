@@ -660,7 +660,7 @@ static void launch_line(const Dir& d, LineArgs<T> a, hipStream_t st) {
   a.nlines = d.nlines;
   a.B = d.B;
   a.logB = d.logB;
-  a.LS = line_stride(d.P);
+  a.LS = d.cols ? cols_line_stride(d.P) : line_stride(d.P);
   a.ls = d.ls;
   a.es = d.es;
   a.ntiles = (d.nlines + d.B - 1) / d.B;
@@ -780,7 +780,7 @@ static void cfft_rows_k(const cx<T>* in, cx<T>* out, int nrows, const cx<T>* Wsu
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set = true;
   }
-  const size_t lds = ((size_t)B * (P + 1) + (size_t)B * P) * sizeof(cx<T>);
+  const size_t lds = ((size_t)B * line_stride(P) + (size_t)B * P) * sizeof(cx<T>);
   hipLaunchKernelGGL((cfft_rows_kernel<T, LOG>), dim3((nrows + B - 1) / B), dim3(B * P / 8), lds, st, in, out, nrows,
                      Wsub, Wbig, twmod, apply, skip, skip2);
 }

@@ -34,7 +34,7 @@ cfft_rows_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int nrow
   constexpr int P = 1 << LOGP;
   constexpr int B = P >= 512 ? 1 : 512 / P;
   constexpr int NTH = B * P / EPT;
-  constexpr int LS = P + 1;
+  constexpr int LS = line_stride(P);   // padded layout of fft_pass (pidx)
   if (skip2f(skip, skip2)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
@@ -62,7 +62,7 @@ cfft_rows_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int nrow
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int e = tid + i * NTH;
-    buf[(e >> LOGP) * LS + (e & (P - 1))] = v[i];
+    buf[(e >> LOGP) * LS + pidx(e & (P - 1))] = v[i];
   }
   __syncthreads();
   fft_lines_ct<T, EPT, LOGP, 0>(buf, LS, tw);
@@ -72,7 +72,7 @@ cfft_rows_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int nrow
     const int l = e >> LOGP, k = e & (P - 1);
     const int r = row0 + l;
     if (r < nrows) {
-      cx<T> x = buf[l * LS + k];
+      cx<T> x = buf[l * LS + pidx(k)];
       if (apply_tw) x = mul(x, Wbig[2 * ((r % twmod) * k)]);
       out[(long)r * P + k] = x;
     }

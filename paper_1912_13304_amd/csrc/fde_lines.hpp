@@ -104,13 +104,21 @@ __device__ __forceinline__ void dftR(cx<T>* v) {
   else dft2(v);
 }
 
-// LDS layout of a line: element i at offset i; lines are P + 1 elements
-// apart.  (A padded layout that spreads the 128-byte lane strides of the
-// first Stockham writes over all banks was measured: it cost more in index
-// arithmetic than it saved in bank conflicts.)
-__device__ __forceinline__ int pidx(int i) { return i; }
+// LDS layout of a line: element i at offset i + i/8.  The first two radix-8
+// Stockham passes write elements 8 and 64 apart from neighbouring lanes;
+// unpadded, those writes fall into a handful of banks (16- and 8-way
+// conflicts), padded they spread over all of them.
+#ifndef FDE_LDS_PAD
+#define FDE_LDS_PAD 1
+#endif
+__host__ __device__ constexpr int pidx(int i) { return FDE_LDS_PAD ? i + (i >> 3) : i; }
 __host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v >> 1); }
-__host__ __device__ constexpr int line_stride(int P) { return P + 1; }
+// Lines of a row tile are pidx(P) + 1 elements apart.
+__host__ __device__ constexpr int line_stride(int P) { return pidx(P) + 1; }
+// Column tiles: a wavefront's elementwise accesses cover 4 lines x 16
+// positions; lines 2(pidx(P) + 8) words apart put those 64 accesses in
+// distinct banks (64 banks of 4 bytes) when pidx(P) is a multiple of 32.
+__host__ __device__ constexpr int cols_line_stride(int P) { return pidx(P) + 8; }
 // Lines per workgroup: rows (contiguous lines) fill one wavefront at least;
 // columns (lines of stride n1) take up to four neighbouring columns, so that
 // every row of the tile is one 16- or 32-byte segment, within 512 threads.
@@ -265,7 +273,7 @@ __global__ void __launch_bounds__(512) line_kernel(LineArgs<T> a) {
   const int P = LOGP > 0 ? CP : a.P;
   const int B = LOGP > 0 ? CB : a.B;
   const int logB = LOGP > 0 ? ilog2c(CB) : a.logB;
-  const int LS = LOGP > 0 ? line_stride(CP) : a.LS;
+  const int LS = LOGP > 0 ? (COLS ? cols_line_stride(CP) : line_stride(CP)) : a.LS;
   const int nth = LOGP > 0 ? CB * CP / EPT : (int)blockDim.x;
   const int tid = threadIdx.x;
   const int n = a.n;
