@@ -108,10 +108,7 @@ __device__ __forceinline__ void dftR(cx<T>* v) {
 // Stockham passes write elements 8 and 64 apart from neighbouring lanes;
 // unpadded, those writes fall into a handful of banks (16- and 8-way
 // conflicts), padded they spread over all of them.
-#ifndef FDE_LDS_PAD
-#define FDE_LDS_PAD 1
-#endif
-__host__ __device__ constexpr int pidx(int i) { return FDE_LDS_PAD ? i + (i >> 3) : i; }
+__host__ __device__ constexpr int pidx(int i) { return i + (i >> 3); }
 __host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v >> 1); }
 // Lines of a row tile are pidx(P) + 1 elements apart.
 __host__ __device__ constexpr int line_stride(int P) { return pidx(P) + 1; }
@@ -132,14 +129,7 @@ __host__ __device__ constexpr int cols_per_tile(int P) {
 // Butterfly j of a line reads x[j + r P/R], multiplies element r by
 // w^(r k) with k = j mod Ls and w = exp(-2 pi i/(Ls R)), applies DFT_R and
 // writes y[(j - k) R + k + r Ls].  In place: all reads finish before a
-// barrier, then all writes.
-// Twiddle w = exp(-i pi m/P) for 0 <= m < 2P from the LDS copy of its first
-// P entries (the second half is the negated first half).
-template <typename T>
-__device__ __forceinline__ cx<T> twiddle(const cx<T>* tw, int m, int P) {
-  const cx<T> t = tw[m < P ? m : m - P];
-  return m < P ? t : mk(-t.x, -t.y);
-}
+// barrier, then all writes.  tw holds exp(-i pi m/P), m < P, in LDS.
 
 template <typename T, int EPT, int R>
 __device__ __forceinline__ void fft_pass(cx<T>* buf, int LS, int logPr, int Ls, int logR,
@@ -165,8 +155,22 @@ __device__ __forceinline__ void fft_pass(cx<T>* buf, int LS, int logPr, int Ls, 
     const int j = jj[s];
     const int k = j & (Ls - 1);
     if (Ls > 1) {
+      // w^k from the table (k << twshift < P), its powers by products of
+      // depth at most 3: one LDS read per butterfly instead of R - 1
+      cx<T> w[R];
+      w[1] = tw[k << twshift];
+      if constexpr (R >= 4) {
+        w[2] = mul(w[1], w[1]);
+        w[3] = mul(w[2], w[1]);
+      }
+      if constexpr (R == 8) {
+        w[4] = mul(w[2], w[2]);
+        w[5] = mul(w[4], w[1]);
+        w[6] = mul(w[3], w[3]);
+        w[7] = mul(w[4], w[3]);
+      }
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[s][r] = mul(v[s][r], twiddle(tw, (r * k) << twshift, P));
+      for (int r = 1; r < R; ++r) v[s][r] = mul(v[s][r], w[r]);
     }
     dftR<T, R>(v[s]);
     const int o = ((j - k) << logR) + k;
@@ -305,9 +309,9 @@ __global__ void __launch_bounds__(512) line_kernel(LineArgs<T> a) {
   // a valid offset) and before any use, so that all loads are in flight
   // together and their latency overlaps the transforms below.
   T xpre[EPT], xpost[EPT], xcp[EPT], xcm[EPT], xb[EPT], xf[EPT];
-  T twr[8], twi[8];
+  T twr[EPT], twi[EPT];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < EPT; ++k) {
     const cx<T> t = a.W2[(tid + k * nth) & (P - 1)];
     twr[k] = t.x;
     twi[k] = t.y;
@@ -331,7 +335,7 @@ __global__ void __launch_bounds__(512) line_kernel(LineArgs<T> a) {
   // their load) with the loads above
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-  for (int k = 0; k < 8; ++k) tw[tid + k * nth] = mk(twr[k], twi[k]);   // B*P >= P slots
+  for (int k = 0; k < EPT; ++k) tw[tid + k * nth] = mk(twr[k], twi[k]);   // B*P >= P slots
   {
     const T sc = a.sc ? (T)(*a.sc) : T(1);
 #pragma unroll
