@@ -29,7 +29,7 @@ PROBE_OFF, PROBE_MAXPY64, PROBE_MDOT64, PROBE_LINE64, PROBE_LINE32, PROBE_MAXPY3
 PROBE_LINE64_VARIANT, PROBE_LINE32_VARIANT = 64, 96
 # line program flags (fde_lines.hpp): DST1 = 1, FDST2 = 2, STOREZ = 4, TOEP = 8, EXTBASE = 16
 LINE_PROGRAMS = {1: "dst", 3: "dst_f_dst", 8: "toeplitz", 11: "dst_f_dst_toeplitz", 12: "storez_toeplitz",
-                 13: "dst_storez_toeplitz", 15: "dst_f_dst_storez_toeplitz"}
+                 13: "dst_storez_toeplitz", 15: "dst_f_dst_storez_toeplitz", 24: "toeplitz_base"}
 
 EXPORTED = ["fde_default_params", "fde_assemble", "fde_matvec", "fde_tau_apply", "fde_solve", "fde_rhs",
             "fde_plan_bytes", "fde_destroy", "fde_last_error", "fde_probe", "fde_probe_read",
