@@ -383,7 +383,7 @@ def main():
         for _ in range(args.warmup):
             job(kw)
         # one untimed job per kernel class: sampled GPU time of each candidate
-        # (every 8th launch of the class is bracketed with HIP events)
+        # (every 32nd launch of the class is bracketed with HIP events)
         shares = {}
         cands = [("cgs_dot64", fde.PROBE_MDOT64), ("cgs_update64", fde.PROBE_MAXPY64),
                  ("cgs_dot32", fde.PROBE_MDOT32), ("cgs_update32", fde.PROBE_MAXPY32)]

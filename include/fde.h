@@ -149,11 +149,17 @@ fde_status fde_rhs(fde_plan plan, const double* u_prev, const double* f, double*
 /* Device bytes a plan with these parameters allocates (for admission control). */
 size_t fde_plan_bytes(const fde_params* p);
 
-/* Releases the plan (synchronises the device first). NULL is ignored. */
+/* Releases the plan (synchronises the device first). NULL is ignored.  The
+   plan's device buffers are kept by the library, per device and size, for
+   the next plan of the same shape (at most 16 GiB in total). */
 void fde_destroy(fde_plan plan);
 
+/* Frees the device buffers the library keeps from destroyed plans
+   (synchronises the current device first).  Plans in use are not affected. */
+void fde_release_cache(void);
+
 /* Kernel timing probe (benchmarking).  fde_probe(plan, cls) starts bracketing
-   every 8th launch of one kernel class issued by this plan with HIP events on
+   every 32nd launch of one kernel class issued by this plan with HIP events on
    the launch stream (a sample keeps the event overhead out of the timing),
    and accumulates those launches' algorithmic bytes (each vector operand read
    or written once); cls = FDE_PROBE_OFF stops.  fde_probe_read synchronises

@@ -85,11 +85,16 @@ struct fde_plan_s {
   // timing probe
   int probe = FDE_PROBE_OFF;
   long long pseen = 0;              // launches of the probed class since fde_probe
-  static constexpr int PSTRIDE = 8; // every PSTRIDE-th launch is bracketed
+  static constexpr int PSTRIDE = 32; // every PSTRIDE-th launch is bracketed
   std::vector<hipEvent_t> pev;      // event pool, pairs (start, stop)
   size_t pused = 0;                 // pairs recorded since the last read
   double pbytes = 0.0;
-  std::vector<void*> allocs;
+  struct Alloc {
+    void* p;
+    size_t bytes;
+    int dev;
+  };
+  std::vector<Alloc> allocs;   // device buffers, returned to the memory cache on destroy
   size_t bytes = 0;
 };
 
@@ -194,9 +199,10 @@ template <typename T>
 static fde_status dalloc(fde_plan pl, T** ptr, size_t count) {
   void* q = nullptr;
   const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-  hipError_t e = hipMalloc(&q, bytes);
+  int dev = 0;
+  hipError_t e = cache_malloc(&q, bytes, &dev);
   if (e != hipSuccess) return fail(FDE_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
-  pl->allocs.push_back(q);
+  pl->allocs.push_back({q, bytes, dev});
   pl->bytes += bytes;
   *ptr = static_cast<T*>(q);
   return FDE_OK;
@@ -253,17 +259,27 @@ static fde_status direction_tables(fde_plan pl, double alpha, int n, cx<double>*
 
 static void destroy_impl(fde_plan pl) {
   if (!pl) return;
-  (void)hipDeviceSynchronize();
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  const int dev = pl->allocs.empty() ? cur : pl->allocs[0].dev;
+  if (dev != cur) (void)hipSetDevice(dev);
+  (void)hipDeviceSynchronize();   // no pending work may touch buffers handed to the cache
   for (auto& e : pl->pev) (void)hipEventDestroy(e);
-  for (void* q : pl->allocs) (void)hipFree(q);
+  for (const auto& a : pl->allocs) cache_free(a.p, a.bytes, a.dev);   // the device is synchronised above
   if (pl->hstat) (void)hipHostFree(pl->hstat);
   if (pl->hks) (void)hipHostFree(pl->hks);
   for (auto& e : pl->ev)
     if (e) (void)hipEventDestroy(e);
+  if (dev != cur) (void)hipSetDevice(cur);
   delete pl;
 }
 
 extern "C" void fde_destroy(fde_plan pl) { destroy_impl(pl); }
+
+extern "C" void fde_release_cache(void) {
+  (void)hipDeviceSynchronize();
+  cache_release();
+}
 
 static fde_status coef_stats(fde_plan pl, const double* a, double* st3, hipStream_t st) {
   double* d = pl->stats_buf;

@@ -10,7 +10,10 @@
 #include <cstdarg>
 #include <algorithm>
 #include <cstdio>
+#include <map>
+#include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/fde.h"
@@ -42,6 +45,72 @@ inline fde_status fail(fde_status st, const char* fmt, ...) {
     fde_status s_ = (expr);         \
     if (s_ != FDE_OK) return s_;    \
   } while (0)
+
+// Device memory cache.  A plan's buffers go back to a per-device list keyed
+// by their exact size when the plan is destroyed (after the device has been
+// synchronised), and the next plan of the same shape takes them instead of
+// calling hipMalloc; hipMalloc and hipFree each cost about a millisecond at
+// these sizes, which a time-stepping job that builds one plan per run would
+// pay every run.  At most CACHE_MAX bytes are held; fde_release_cache frees
+// them.  Blocks are handed out uninitialised, as hipMalloc's are.
+struct MemCache {
+  static constexpr size_t CACHE_MAX = size_t(16) << 30;
+  std::mutex mu;
+  std::map<std::pair<int, size_t>, std::vector<void*>> blocks;
+  size_t held = 0;
+};
+
+inline MemCache& memcache() {
+  static MemCache* c = new MemCache();   // never destroyed: no hipFree after the runtime is gone
+  return *c;
+}
+
+inline hipError_t cache_malloc(void** p, size_t bytes, int* dev_out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  *dev_out = dev;
+  {
+    MemCache& c = memcache();
+    std::lock_guard<std::mutex> g(c.mu);
+    auto it = c.blocks.find({dev, bytes});
+    if (it != c.blocks.end() && !it->second.empty()) {
+      *p = it->second.back();
+      it->second.pop_back();
+      c.held -= bytes;
+      return hipSuccess;
+    }
+  }
+  return hipMalloc(p, bytes);
+}
+
+// The device that owns p must have no pending work on it.
+inline void cache_free(void* p, size_t bytes, int dev) {
+  MemCache& c = memcache();
+  {
+    std::lock_guard<std::mutex> g(c.mu);
+    if (c.held + bytes <= MemCache::CACHE_MAX) {
+      c.blocks[{dev, bytes}].push_back(p);
+      c.held += bytes;
+      return;
+    }
+  }
+  (void)hipFree(p);
+}
+
+inline void cache_release() {
+  MemCache& c = memcache();
+  std::lock_guard<std::mutex> g(c.mu);
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  for (auto& kv : c.blocks) {
+    (void)hipSetDevice(kv.first.first);
+    for (void* q : kv.second) (void)hipFree(q);
+  }
+  (void)hipSetDevice(cur);
+  c.blocks.clear();
+  c.held = 0;
+}
 
 inline int ilog2(long v) {
   int l = 0;

@@ -32,7 +32,7 @@ LINE_PROGRAMS = {1: "dst", 3: "dst_f_dst", 8: "toeplitz", 11: "dst_f_dst_toeplit
                  13: "dst_storez_toeplitz", 15: "dst_f_dst_storez_toeplitz", 24: "toeplitz_base"}
 
 EXPORTED = ["fde_default_params", "fde_assemble", "fde_matvec", "fde_tau_apply", "fde_solve", "fde_rhs",
-            "fde_plan_bytes", "fde_destroy", "fde_last_error", "fde_probe", "fde_probe_read",
+            "fde_plan_bytes", "fde_destroy", "fde_release_cache", "fde_last_error", "fde_probe", "fde_probe_read",
             "fde_batch_layout", "fde_batch_bytes", "fde_batch_assemble", "fde_batch_solve", "fde_batch_run",
             "fde_batch_tune", "fde_batch_get_cfg", "fde_batch_set_cfg", "fde_batch_destroy",
             "fde_batch_matvec", "fde_batch_tau_apply"]
@@ -117,6 +117,8 @@ def load(path: str = LIB_PATH):
     lib.fde_plan_bytes.restype = ctypes.c_size_t
     lib.fde_destroy.argtypes = [vp]
     lib.fde_destroy.restype = None
+    lib.fde_release_cache.argtypes = []
+    lib.fde_release_cache.restype = None
     lib.fde_probe.argtypes = [vp, ctypes.c_int]
     lib.fde_probe.restype = ctypes.c_int
     lib.fde_probe_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong),
@@ -241,6 +243,10 @@ def fde_plan_bytes(params: FdeParams) -> int:
 def fde_destroy(plan):
     if plan:
         load().fde_destroy(plan)
+
+
+def fde_release_cache():
+    load().fde_release_cache()
 
 
 def fde_probe(plan, cls):

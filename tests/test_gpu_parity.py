@@ -328,3 +328,34 @@ def test_tri_rejected_in_2d_and_without_dominance():
     with pytest.raises(fde.FdeError) as e:
         fde.Plan(prob1d(63, weights="weighted", time="cn"), prec=fde.P_TRI)
     assert e.value.status == fde.FDE_EINVAL
+
+
+def test_plan_buffers_reused_and_released():
+    """Plans of one shape built one after another take the buffers the
+    previous one left in the library's cache (stale contents); their solves
+    are bit-identical, also after the cache is released, and a plan of
+    another shape in between does not disturb them."""
+    fde = need_gpu()
+    p = prob2d(127, 255)
+    q = prob1d(1023)
+    s = FDESystem.from_problem(p)
+    b = s.rhs(p.u0.reshape(-1))
+    res = []
+    for step in range(4):
+        if step == 2:
+            fde.fde_release_cache()
+        if step == 3:
+            with fde.Plan(q, precision=fde.MIXED) as other:
+                x = dev(q.u0)
+                other.solve(dev(FDESystem.from_problem(q).rhs(q.u0)), x)
+        for precision in (fde.FP64, fde.MIXED):
+            with fde.Plan(p, precision=precision) as plan:
+                x = dev(p.u0.reshape(-1))
+                info = plan.solve(dev(b), x)
+                res.append((precision, host(x), info.iters))
+    for precision in (fde.FP64, fde.MIXED):
+        runs = [r for r in res if r[0] == precision]
+        for r in runs[1:]:
+            assert r[2] == runs[0][2]
+            assert np.array_equal(r[1], runs[0][1])
+        assert relerr(s.matvec(runs[0][1]), b) <= 1e-8 * (1 + 1e-6)
