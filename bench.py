@@ -431,22 +431,24 @@ def main():
             f"{results[name]['ms_per_solve']:.2f} ms/solve, {results[name]['iters_per_solve']:.1f} it/solve")
 
     # served leg: Poisson arrivals of mixed 1D / 2D time-stepping requests,
-    # continuous batching over slots x streams, mixed precision
+    # continuous batching over slots x streams; each request in its faster
+    # form (mixed for 2D, float64 for 1D)
     served = None
     if args.serve_count > 0:
         from paper_1912_13304_amd import serve
         arr = fi.served_stream(args.serve_rate, args.serve_count, seed=5, n1d=(1023, 65535))
-        serve.serve_stream(arr[:4], slots=args.serve_slots, precision=fde.MIXED, inner_steps=args.inner)  # warm
-        res, wall = serve.serve_stream(arr, slots=args.serve_slots, precision=fde.MIXED, inner_steps=args.inner)
+        serve.serve_stream(arr[:4], slots=args.serve_slots, precision=serve.AUTO, inner_steps=args.inner)  # warm
+        res, wall = serve.serve_stream(arr, slots=args.serve_slots, precision=serve.AUTO, inner_steps=args.inner)
         served = serve.latency_stats(res)
         served.update(rate_req_per_s=args.serve_rate, slots=args.serve_slots,
                       mix="70% 1D n log-uniform in [1023, 65535] rounded to 2^k-1, 30% 2D n in "
-                          "{127,255,511,1023}; 5-50 steps; alpha ~ U(1.1,1.9); mixed precision, tol 1e-8")
+                          "{127,255,511,1023}; 5-50 steps; alpha ~ U(1.1,1.9); tol 1e-8; mixed precision "
+                          "for 2D requests, float64 for 1D requests")
         log(f"[bench] served: {served}")
         sweep = []
         for r in [float(x) for x in args.serve_sweep.split(",") if x.strip()]:
             arr = fi.served_stream(r, args.serve_count, seed=5, n1d=(1023, 65535))
-            res, wall = serve.serve_stream(arr, slots=args.serve_slots, precision=fde.MIXED, inner_steps=args.inner)
+            res, wall = serve.serve_stream(arr, slots=args.serve_slots, precision=serve.AUTO, inner_steps=args.inner)
             st = serve.latency_stats(res)
             st.update(rate_req_per_s=r)
             sweep.append(st)

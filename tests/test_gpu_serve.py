@@ -14,7 +14,7 @@ def small_stream(rate=2000.0, count=8, seed=21):
     return fi.served_stream(rate, count, seed=seed, n1d=(255, 4095), n2d=(63, 127, 255), steps=(2, 5))
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, "auto"])
 def test_alone_equals_mix(precision):
     fde = need_gpu()
     from paper_1912_13304_amd import serve
@@ -27,7 +27,7 @@ def test_alone_equals_mix(precision):
     spans = sorted((r.start, r.finish) for r in results)
     assert any(spans[i + 1][0] < spans[i][1] for i in range(len(spans) - 1))
     for a in arr:
-        infos, u = serve.run_job(a.problem, keep_state=True, **kw)
+        infos, u = serve.run_job(a.problem, keep_state=True, **serve.request_kw(a.problem, kw))
         torch.cuda.synchronize()
         r = by_name[a.problem.name]
         assert r.iters == [i.iters for i in infos]
