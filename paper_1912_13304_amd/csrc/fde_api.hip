@@ -785,53 +785,56 @@ static void add_y_part(fde_plan pl, const T* x, const T* xpart, T* y, T tscale, 
 // ---------------------------------------------------------------------------
 // Big 1D lines (P > 4096)
 // ---------------------------------------------------------------------------
-template <typename T, int LOG>
-static void cfft_rows_k(const cx<T>* in, cx<T>* out, int nrows, const cx<T>* Wsub, const cx<T>* Wbig, int twmod,
-                        int apply, hipStream_t st, const int* skip, const int* skip2) {
-  constexpr int P = 1 << LOG;
-  constexpr int B = P >= 512 ? 1 : 512 / P;
+template <typename T, int LOG, bool CIN, bool COUT>
+static void fourstep_k(const cx<T>* in, cx<T>* out, long P, int npl, int batch, long ils, long ies, long ols,
+                       long oes, const cx<T>* Wsub, const cx<T>* Wbig, int apply, hipStream_t st, const int* skip,
+                       const int* skip2) {
+  constexpr int L = 1 << LOG;
+  constexpr int B = L >= 512 ? 1 : 512 / L;
   static bool attr_set = false;
   if (!attr_set) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&cfft_rows_kernel<T, LOG>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&fourstep_kernel<T, LOG, CIN, COUT>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set = true;
   }
-  const size_t lds = ((size_t)B * line_stride(P) + (size_t)B * P) * sizeof(cx<T>);
-  hipLaunchKernelGGL((cfft_rows_kernel<T, LOG>), dim3((nrows + B - 1) / B), dim3(B * P / 8), lds, st, in, out, nrows,
-                     Wsub, Wbig, twmod, apply, skip, skip2);
+  const size_t lds = ((size_t)B * line_stride(L) + (size_t)B * L) * sizeof(cx<T>);
+  const long lines = (long)batch * npl;   // B divides npl (both powers of two, npl >= 64 >= B)
+  hipLaunchKernelGGL((fourstep_kernel<T, LOG, CIN, COUT>), dim3((unsigned)(lines / B)), dim3(B * L / 8), lds, st, in,
+                     out, P, npl, ils, ies, ols, oes, Wsub, Wbig, apply, skip, skip2);
 }
 
-template <typename T>
-static void cfft_rows(int lg, const cx<T>* in, cx<T>* out, int nrows, const cx<T>* Wsub, const cx<T>* Wbig,
-                      int twmod, int apply, hipStream_t st, const int* skip, const int* skip2) {
+// Column pass (lines = the P2 columns of the P1 x P2 view, length P1, in
+// place layout, twiddled) or row pass (lines = the P1 rows, length P2,
+// written in natural order).
+template <typename T, bool COLPASS>
+static void fourstep(int lg, const cx<T>* in, cx<T>* out, long P, int P1, int P2, int batch, const cx<T>* Wsub,
+                     const cx<T>* Wbig, hipStream_t st, const int* skip, const int* skip2) {
+#define FDE_FOURSTEP_CASE(LG)                                                                                   \
+  case LG:                                                                                                     \
+    if (COLPASS)                                                                                               \
+      fourstep_k<T, LG, true, true>(in, out, P, P2, batch, 1, P2, 1, P2, Wsub, Wbig, 1, st, skip, skip2);     \
+    else                                                                                                       \
+      fourstep_k<T, LG, false, true>(in, out, P, P1, batch, P2, 1, 1, P1, Wsub, Wbig, 0, st, skip, skip2);    \
+    break;
   switch (lg) {
-    case 6: cfft_rows_k<T, 6>(in, out, nrows, Wsub, Wbig, twmod, apply, st, skip, skip2); break;
-    case 7: cfft_rows_k<T, 7>(in, out, nrows, Wsub, Wbig, twmod, apply, st, skip, skip2); break;
-    case 8: cfft_rows_k<T, 8>(in, out, nrows, Wsub, Wbig, twmod, apply, st, skip, skip2); break;
-    case 9: cfft_rows_k<T, 9>(in, out, nrows, Wsub, Wbig, twmod, apply, st, skip, skip2); break;
-    case 10: cfft_rows_k<T, 10>(in, out, nrows, Wsub, Wbig, twmod, apply, st, skip, skip2); break;
-    case 11: cfft_rows_k<T, 11>(in, out, nrows, Wsub, Wbig, twmod, apply, st, skip, skip2); break;
-    default: cfft_rows_k<T, 11>(in, out, nrows, Wsub, Wbig, twmod, apply, st, skip, skip2); break;
+    FDE_FOURSTEP_CASE(6)
+    FDE_FOURSTEP_CASE(7)
+    FDE_FOURSTEP_CASE(8)
+    FDE_FOURSTEP_CASE(9)
+    FDE_FOURSTEP_CASE(10)
+    FDE_FOURSTEP_CASE(11)
+    default: break;   // P = n + 1 <= 2^22: both factors have 6..11 bits
   }
+#undef FDE_FOURSTEP_CASE
 }
 
-template <typename T>
-static void ctranspose(const cx<T>* in, cx<T>* out, int rows, int cols, int batch, hipStream_t st, const int* skip,
-                       const int* skip2) {
-  const dim3 g((cols + 31) / 32, (rows + 31) / 32, batch);
-  hipLaunchKernelGGL((ctranspose_kernel<T>), g, dim3(256), 0, st, in, out, rows, cols, skip, skip2);
-}
-
-// b = FFT_P(a) for `batch` consecutive lines of P complex values; a is clobbered.
+// P-point FFT of `batch` arrays in a (natural order in and out); b is scratch.
 template <typename T>
 static void big_fft(fde_plan pl, cx<T>* a, cx<T>* b, int batch, hipStream_t st, const int* skip, const int* skip2) {
   const Consts<T>& c = consts<T>(pl);
-  const int P1 = pl->P1, P2 = pl->P2;
-  ctranspose<T>(a, b, P1, P2, batch, st, skip, skip2);                                     // [j2][j1]
-  cfft_rows<T>(pl->log1, b, a, batch * P2, c.W2p1, c.W2x, P2, 1, st, skip, skip2);         // [j2][k1] * w
-  ctranspose<T>(a, b, P2, P1, batch, st, skip, skip2);                                     // [k1][j2]
-  cfft_rows<T>(pl->log2, b, a, batch * P1, c.W2p2, c.W2x, 1, 0, st, skip, skip2);          // [k1][k2]
-  ctranspose<T>(a, b, P1, P2, batch, st, skip, skip2);                                     // [k2][k1]
+  const long P = pl->rows.P;
+  fourstep<T, true>(pl->log1, a, b, P, pl->P1, pl->P2, batch, c.W2p1, c.W2x, st, skip, skip2);    // columns
+  fourstep<T, false>(pl->log2, b, a, P, pl->P1, pl->P2, batch, c.W2p2, c.W2x, st, skip, skip2);   // rows
 }
 
 static int ew_grid(long N);
@@ -847,8 +850,8 @@ static void big_tau(fde_plan pl, const T* v, const double* sc, const T* pre, con
   const int g = ew_grid(P);
   hipLaunchKernelGGL((pack_dst_kernel<T>), dim3(g), dim3(256), 0, st, v, pre, sc, c0, n, P, skip, skip2);
   big_fft<T>(pl, c0, c1, 1, st, skip, skip2);
-  hipLaunchKernelGGL((unpack_f_pack_kernel<T>), dim3(g), dim3(256), 0, st, c1, c.W2x, c.fx, c0, P, skip, skip2);
-  big_fft<T>(pl, c0, c1, 1, st, skip, skip2);
+  hipLaunchKernelGGL((unpack_f_pack_kernel<T>), dim3(g), dim3(256), 0, st, c0, c.W2x, c.fx, c1, P, skip, skip2);
+  big_fft<T>(pl, c1, c0, 1, st, skip, skip2);
   hipLaunchKernelGGL((unpack_dst_kernel<T>), dim3(g), dim3(256), 0, st, c1, c.W2x, post, z, z2, n, P, skip, skip2);
 }
 
@@ -865,9 +868,9 @@ static void big_toep(fde_plan pl, const T* x, const T* base, T bscale, T tscale,
   const int g = ew_grid(P);
   hipLaunchKernelGGL((pack_toep_kernel<T>), dim3(g), dim3(256), 0, st, x, c0, n, P, skip, skip2);
   big_fft<T>(pl, c0, c1, 1, st, skip, skip2);
-  hipLaunchKernelGGL((pair_toep_kernel<T>), dim3(g), dim3(256), 0, st, c1, c.lamx, c.W2x, c2, c2 + P, P, skip, skip2);
+  hipLaunchKernelGGL((pair_toep_kernel<T>), dim3(g), dim3(256), 0, st, c0, c.lamx, c.W2x, c2, c2 + P, P, skip, skip2);
   big_fft<T>(pl, c2, c3, 2, st, skip, skip2);
-  hipLaunchKernelGGL((extract_toep_kernel<T>), dim3(g), dim3(256), 0, st, c3, c3 + P, c.dp, c.dm, base, bscale, tscale,
+  hipLaunchKernelGGL((extract_toep_kernel<T>), dim3(g), dim3(256), 0, st, c2, c2 + P, c.dp, c.dm, base, bscale, tscale,
                      out, n, P, skip, skip2);
 }
 

@@ -1,10 +1,13 @@
 // Transforms of one 1D line longer than a workgroup holds (P = n + 1 > 4096).
 //
-// The complex P-point FFT is a four-step FFT over kernels, P = P1 * P2 with
-// both factors <= 4096: view x (j = j1 P2 + j2) as a P1 x P2 array,
-// transpose, FFT the P2 rows of length P1 and multiply entry (j2, k1) by
-// exp(-2 pi i j2 k1 / P), transpose, FFT the P1 rows of length P2, transpose:
-// X[k1 + P1 k2] lands at position k2 P1 + k1, the natural order.
+// The complex P-point FFT is a four-step FFT in two kernels, P = P1 * P2
+// with both factors <= 4096: view x (j = j1 P2 + j2) as a P1 x P2 array;
+// the first pass transforms its P2 columns (length P1, read and written in
+// place with stride P2) and multiplies entry (k1, j2) by
+// exp(-2 pi i j2 k1 / P); the second transforms the P1 rows (length P2) and
+// writes X[k1 + P1 k2] to position k1 + P1 k2, the natural order.  A
+// workgroup takes neighbouring columns (rows), so that the strided accesses
+// of a wavefront are segments of neighbouring elements.
 //
 // The DST-I and Toeplitz programs use the same packings as the one-workgroup
 // line kernels (odd extension / zero padding packed into P complex points,
@@ -22,60 +25,70 @@ namespace fde {
 
 __device__ __forceinline__ bool skip2f(const int* a, const int* b) { return (a && *a) || (b && *b); }
 
-// Rows of length P = 2^LOGP (row-major complex array of nrows rows): FFT of
-// every row; with apply_tw, entry (r, k) is then multiplied by
-// exp(-2 pi i (r mod twmod) k / Pbig) = Wbig[2 ((r mod twmod) k)], where Wbig
-// is the table exp(-i pi m / Pbig), m < 2 Pbig.
-template <typename T, int LOGP>
+// One pass of the four-step FFT: FFTs of length L = 2^LOGL on lines of a
+// batch of P-point arrays; line g (item z = g / npl, q = g mod npl) has its
+// elements at in[z P + q ils + m ies] and writes them to
+// out[z P + q ols + k oes].  CIN / COUT: the lines are 1 element apart
+// (ils == 1 / ols == 1), so neighbouring threads take neighbouring lines
+// there.  apply_tw multiplies entry (q, k) by Wbig[2 q k] =
+// exp(-2 pi i q k / P).  B = max(1, 512 / L) lines per workgroup (B divides
+// npl), B L / 8 threads.
+template <typename T, int LOGL, bool CIN, bool COUT>
 __global__ void __launch_bounds__(512)
-cfft_rows_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int nrows, const cx<T>* __restrict__ Wsub,
-                 const cx<T>* __restrict__ Wbig, int twmod, int apply_tw, const int* skip, const int* skip2) {
+fourstep_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, long P, int npl, long ils, long ies,
+                long ols, long oes, const cx<T>* __restrict__ Wsub, const cx<T>* __restrict__ Wbig, int apply_tw,
+                const int* skip, const int* skip2) {
   constexpr int EPT = 8;
-  constexpr int P = 1 << LOGP;
-  constexpr int B = P >= 512 ? 1 : 512 / P;
-  constexpr int NTH = B * P / EPT;
-  constexpr int LS = line_stride(P);   // padded layout of fft_pass (pidx)
+  constexpr int L = 1 << LOGL;
+  constexpr int B = L >= 512 ? 1 : 512 / L;
+  constexpr int LOGB = ilog2c(B);
+  constexpr int NTH = B * L / EPT;
+  constexpr int LS = line_stride(L);
   if (skip2f(skip, skip2)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* tw = buf + B * LS;
   const int tid = threadIdx.x;
-  const int row0 = blockIdx.x * B;
+  const long g0 = (long)blockIdx.x * B;
+  const long z = g0 / npl;
+  const int q0 = (int)(g0 - z * npl);
+  const cx<T>* src = in + z * P;
+  cx<T>* dst = out + z * P;
   cx<T> v[EPT];
-  T twr[8], twi[8];
+  T twr[EPT], twi[EPT];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const cx<T> t = Wsub[(tid + k * NTH) & (P - 1)];
+  for (int k = 0; k < EPT; ++k) {
+    const cx<T> t = Wsub[(tid + k * NTH) & (L - 1)];
     twr[k] = t.x;
     twi[k] = t.y;
   }
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int e = tid + i * NTH;
-    const int l = e >> LOGP, m = e & (P - 1);
-    const int r = min(row0 + l, nrows - 1);
-    v[i] = in[(long)r * P + m];
+    const int l = CIN ? (e & (B - 1)) : (e >> LOGL);
+    const int m = CIN ? (e >> LOGB) : (e & (L - 1));
+    v[i] = src[(long)(q0 + l) * ils + (long)m * ies];
   }
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-  for (int k = 0; k < 8; ++k) tw[tid + k * NTH] = mk(twr[k], twi[k]);
+  for (int k = 0; k < EPT; ++k) tw[tid + k * NTH] = mk(twr[k], twi[k]);
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int e = tid + i * NTH;
-    buf[(e >> LOGP) * LS + pidx(e & (P - 1))] = v[i];
+    const int l = CIN ? (e & (B - 1)) : (e >> LOGL);
+    const int m = CIN ? (e >> LOGB) : (e & (L - 1));
+    buf[l * LS + pidx(m)] = v[i];
   }
   __syncthreads();
-  fft_lines_ct<T, EPT, LOGP, 0>(buf, LS, tw);
+  fft_lines_ct<T, EPT, LOGL, 0>(buf, LS, tw);
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int e = tid + i * NTH;
-    const int l = e >> LOGP, k = e & (P - 1);
-    const int r = row0 + l;
-    if (r < nrows) {
-      cx<T> x = buf[l * LS + pidx(k)];
-      if (apply_tw) x = mul(x, Wbig[2 * ((r % twmod) * k)]);
-      out[(long)r * P + k] = x;
-    }
+    const int l = COUT ? (e & (B - 1)) : (e >> LOGL);
+    const int k = COUT ? (e >> LOGB) : (e & (L - 1));
+    cx<T> x = buf[l * LS + pidx(k)];
+    if (apply_tw) x = mul(x, Wbig[2 * (long)(q0 + l) * k]);
+    dst[(long)(q0 + l) * ols + (long)k * oes] = x;
   }
 }
 
@@ -198,32 +211,6 @@ __global__ void extract_toep_kernel(const cx<T>* R1, const cx<T>* R2, const T* c
     const T y1 = ((m & 1) ? -r1.y : r1.x) * invP;
     const T y2 = ((m & 1) ? -r2.y : r2.x) * invP;
     out[m] = bscale * base[m] + tscale * (cplus[m] * y1 + cminus[m] * y2);
-  }
-}
-
-// Batched complex transpose: for each z < batch, out_z (cols x rows) = in_z^T.
-template <typename T>
-__global__ void __launch_bounds__(256)
-ctranspose_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int rows, int cols, const int* skip,
-                  const int* skip2) {
-  if (skip2f(skip, skip2)) return;
-  __shared__ cx<T> tile[32][33];
-  const long zoff = (long)blockIdx.z * rows * cols;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
-  cx<T> t[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int r = min(r0 + ty + 8 * i, rows - 1), c = min(c0 + tx, cols - 1);
-    t[i] = in[zoff + (long)r * cols + c];
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) tile[ty + 8 * i][tx] = t[i];
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int c = c0 + ty + 8 * i, r = r0 + tx;
-    if (c < cols && r < rows) out[zoff + (long)c * rows + r] = tile[tx][ty + 8 * i];
   }
 }
 

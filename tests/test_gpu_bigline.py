@@ -12,8 +12,9 @@ from oracle.system import FDESystem
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("n", [8191, 65535, 262143])
-@pytest.mark.parametrize("weights,time", [("shifted", "euler"), ("weighted", "cn")])
+@pytest.mark.parametrize("n,weights,time", [(n, w, t) for n in (8191, 65535, 262143)
+                                             for w, t in (("shifted", "euler"), ("weighted", "cn"))]
+                         + [(2097151, "shifted", "euler"), (4194303, "weighted", "cn")])
 def test_big_matvec_and_tau(n, weights, time):
     fde = need_gpu()
     p = fi.variable_1d(n=n, alpha=1.37, seed=n)
