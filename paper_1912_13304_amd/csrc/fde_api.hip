@@ -785,33 +785,33 @@ static void add_y_part(fde_plan pl, const T* x, const T* xpart, T* y, T tscale, 
 // ---------------------------------------------------------------------------
 // Big 1D lines (P > 4096)
 // ---------------------------------------------------------------------------
-template <typename T, int LOG, bool CIN, bool COUT>
-static void fourstep_k(const cx<T>* in, cx<T>* out, long P, int npl, int batch, long ils, long ies, long ols,
-                       long oes, const cx<T>* Wsub, const cx<T>* Wbig, int apply, hipStream_t st, const int* skip,
+template <typename T, int LOG, bool CIN, bool COUT, class LD>
+static void fourstep_k(LD in, cx<T>* out, long P, int npl, int batch, long ils, long ies, long ols, long oes,
+                       const cx<T>* Wsub, const cx<T>* Wbig, int apply, hipStream_t st, const int* skip,
                        const int* skip2) {
   constexpr int L = 1 << LOG;
   constexpr int B = L >= 512 ? 1 : 512 / L;
   static bool attr_set = false;
   if (!attr_set) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&fourstep_kernel<T, LOG, CIN, COUT>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&fourstep_kernel<T, LOG, CIN, COUT, LD>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set = true;
   }
   const size_t lds = ((size_t)B * line_stride(L) + (size_t)B * L) * sizeof(cx<T>);
   const long lines = (long)batch * npl;   // B divides npl (both powers of two, npl >= 64 >= B)
-  hipLaunchKernelGGL((fourstep_kernel<T, LOG, CIN, COUT>), dim3((unsigned)(lines / B)), dim3(B * L / 8), lds, st, in,
+  hipLaunchKernelGGL((fourstep_kernel<T, LOG, CIN, COUT, LD>), dim3((unsigned)(lines / B)), dim3(B * L / 8), lds, st, in,
                      out, P, npl, ils, ies, ols, oes, Wsub, Wbig, apply, skip, skip2);
 }
 
 // Column pass (lines = the P2 columns of the P1 x P2 view, length P1, in
 // place layout, twiddled) or row pass (lines = the P1 rows, length P2,
 // written in natural order).
-template <typename T, bool COLPASS>
-static void fourstep(int lg, const cx<T>* in, cx<T>* out, long P, int P1, int P2, int batch, const cx<T>* Wsub,
+template <typename T, bool COLPASS, class LD>
+static void fourstep(int lg, LD in, cx<T>* out, long P, int P1, int P2, int batch, const cx<T>* Wsub,
                      const cx<T>* Wbig, hipStream_t st, const int* skip, const int* skip2) {
 #define FDE_FOURSTEP_CASE(LG)                                                                                   \
   case LG:                                                                                                     \
-    if (COLPASS)                                                                                               \
+    if constexpr (COLPASS)                                                                                     \
       fourstep_k<T, LG, true, true>(in, out, P, P2, batch, 1, P2, 1, P2, Wsub, Wbig, 1, st, skip, skip2);     \
     else                                                                                                       \
       fourstep_k<T, LG, false, true>(in, out, P, P1, batch, P2, 1, 1, P1, Wsub, Wbig, 0, st, skip, skip2);    \
@@ -828,13 +828,18 @@ static void fourstep(int lg, const cx<T>* in, cx<T>* out, long P, int P1, int P2
 #undef FDE_FOURSTEP_CASE
 }
 
-// P-point FFT of `batch` arrays in a (natural order in and out); b is scratch.
-template <typename T>
-static void big_fft(fde_plan pl, cx<T>* a, cx<T>* b, int batch, hipStream_t st, const int* skip, const int* skip2) {
+// P-point FFT of the `batch` arrays the loader produces, into `out`
+// (natural order); `tmp` (batch P entries) is scratch.  The column pass has
+// finished reading the loader's sources before the row pass writes `out`, so
+// `out` may be one of them.
+template <typename T, class LD>
+static void big_fft(fde_plan pl, LD ld, cx<T>* out, cx<T>* tmp, int batch, hipStream_t st, const int* skip,
+                    const int* skip2) {
   const Consts<T>& c = consts<T>(pl);
   const long P = pl->rows.P;
-  fourstep<T, true>(pl->log1, a, b, P, pl->P1, pl->P2, batch, c.W2p1, c.W2x, st, skip, skip2);    // columns
-  fourstep<T, false>(pl->log2, b, a, P, pl->P1, pl->P2, batch, c.W2p2, c.W2x, st, skip, skip2);   // rows
+  fourstep<T, true>(pl->log1, ld, tmp, P, pl->P1, pl->P2, batch, c.W2p1, c.W2x, st, skip, skip2);   // columns
+  fourstep<T, false>(pl->log2, LdArray<T>{tmp, P}, out, P, pl->P1, pl->P2, batch, c.W2p2, c.W2x, st, skip,
+                     skip2);                                                                          // rows
 }
 
 static int ew_grid(long N);
@@ -848,11 +853,9 @@ static void big_tau(fde_plan pl, const T* v, const double* sc, const T* pre, con
   cx<T>* c0 = c.cw;
   cx<T>* c1 = c.cw + P;
   const int g = ew_grid(P);
-  hipLaunchKernelGGL((pack_dst_kernel<T>), dim3(g), dim3(256), 0, st, v, pre, sc, c0, n, P, skip, skip2);
-  big_fft<T>(pl, c0, c1, 1, st, skip, skip2);
-  hipLaunchKernelGGL((unpack_f_pack_kernel<T>), dim3(g), dim3(256), 0, st, c0, c.W2x, c.fx, c1, P, skip, skip2);
-  big_fft<T>(pl, c1, c0, 1, st, skip, skip2);
-  hipLaunchKernelGGL((unpack_dst_kernel<T>), dim3(g), dim3(256), 0, st, c1, c.W2x, post, z, z2, n, P, skip, skip2);
+  big_fft<T>(pl, LdPackDst<T>{v, pre, sc, P}, c0, c1, 1, st, skip, skip2);
+  big_fft<T>(pl, LdFRepack<T>{c0, c.W2x, c.fx, P}, c0, c1, 1, st, skip, skip2);
+  hipLaunchKernelGGL((unpack_dst_kernel<T>), dim3(g), dim3(256), 0, st, c0, c.W2x, post, z, z2, n, P, skip, skip2);
 }
 
 // out = bscale * base + tscale * (D+ T x + D- T^T x)   (1D big line)
@@ -866,11 +869,9 @@ static void big_toep(fde_plan pl, const T* x, const T* base, T bscale, T tscale,
   cx<T>* c2 = c.cw + 2 * P;
   cx<T>* c3 = c.cw + 4 * P;
   const int g = ew_grid(P);
-  hipLaunchKernelGGL((pack_toep_kernel<T>), dim3(g), dim3(256), 0, st, x, c0, n, P, skip, skip2);
-  big_fft<T>(pl, c0, c1, 1, st, skip, skip2);
-  hipLaunchKernelGGL((pair_toep_kernel<T>), dim3(g), dim3(256), 0, st, c0, c.lamx, c.W2x, c2, c2 + P, P, skip, skip2);
-  big_fft<T>(pl, c2, c3, 2, st, skip, skip2);
-  hipLaunchKernelGGL((extract_toep_kernel<T>), dim3(g), dim3(256), 0, st, c2, c2 + P, c.dp, c.dm, base, bscale, tscale,
+  big_fft<T>(pl, LdPackToep<T>{x, n}, c0, c1, 1, st, skip, skip2);
+  big_fft<T>(pl, LdPairToep<T>{c0, c.lamx, c.W2x, P}, c3, c2, 2, st, skip, skip2);
+  hipLaunchKernelGGL((extract_toep_kernel<T>), dim3(g), dim3(256), 0, st, c3, c3 + P, c.dp, c.dm, base, bscale, tscale,
                      out, n, P, skip, skip2);
 }
 

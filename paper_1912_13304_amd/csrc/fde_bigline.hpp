@@ -26,18 +26,19 @@ namespace fde {
 __device__ __forceinline__ bool skip2f(const int* a, const int* b) { return (a && *a) || (b && *b); }
 
 // One pass of the four-step FFT: FFTs of length L = 2^LOGL on lines of a
-// batch of P-point arrays; line g (item z = g / npl, q = g mod npl) has its
-// elements at in[z P + q ils + m ies] and writes them to
+// batch of P-point arrays; line g (item z = g / npl, q = g mod npl) takes
+// its elements from the loader, in(z, q ils + m ies) (an array, or one of
+// the packings below computed on the fly), and writes them to
 // out[z P + q ols + k oes].  CIN / COUT: the lines are 1 element apart
 // (ils == 1 / ols == 1), so neighbouring threads take neighbouring lines
 // there.  apply_tw multiplies entry (q, k) by Wbig[2 q k] =
 // exp(-2 pi i q k / P).  B = max(1, 512 / L) lines per workgroup (B divides
 // npl), B L / 8 threads.
-template <typename T, int LOGL, bool CIN, bool COUT>
+template <typename T, int LOGL, bool CIN, bool COUT, class LD>
 __global__ void __launch_bounds__(512)
-fourstep_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, long P, int npl, long ils, long ies,
-                long ols, long oes, const cx<T>* __restrict__ Wsub, const cx<T>* __restrict__ Wbig, int apply_tw,
-                const int* skip, const int* skip2) {
+fourstep_kernel(LD in, cx<T>* __restrict__ out, long P, int npl, long ils, long ies, long ols, long oes,
+                const cx<T>* __restrict__ Wsub, const cx<T>* __restrict__ Wbig, int apply_tw, const int* skip,
+                const int* skip2) {
   constexpr int EPT = 8;
   constexpr int L = 1 << LOGL;
   constexpr int B = L >= 512 ? 1 : 512 / L;
@@ -52,7 +53,6 @@ fourstep_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, long P, i
   const long g0 = (long)blockIdx.x * B;
   const long z = g0 / npl;
   const int q0 = (int)(g0 - z * npl);
-  const cx<T>* src = in + z * P;
   cx<T>* dst = out + z * P;
   cx<T> v[EPT];
   T twr[EPT], twi[EPT];
@@ -67,7 +67,7 @@ fourstep_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, long P, i
     const int e = tid + i * NTH;
     const int l = CIN ? (e & (B - 1)) : (e >> LOGL);
     const int m = CIN ? (e >> LOGB) : (e & (L - 1));
-    v[i] = src[(long)(q0 + l) * ils + (long)m * ies];
+    v[i] = in(z, (long)(q0 + l) * ils + (long)m * ies);
   }
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -92,22 +92,37 @@ fourstep_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, long P, i
   }
 }
 
+// Loaders of the column pass.  Each returns entry j of item z of the array
+// the pass transforms.
+
+// The array itself.
+template <typename T>
+struct LdArray {
+  const cx<T>* a;
+  long P;
+  __device__ cx<T> operator()(long z, long j) const { return a[z * P + j]; }
+};
+
 // DST packing: z_j = u_{2j} + i u_{2j+1}, u the odd extension (length 2P) of
 // x_m = sc * pre_m * in_{m-1}, m = 1..n (u_0 = u_P = 0, u_{2P-m} = -x_m).
 template <typename T>
-__global__ void pack_dst_kernel(const T* in, const T* pre, const double* sc, cx<T>* z, int n, int P,
-                                const int* skip, const int* skip2) {
-  if (skip2f(skip, skip2)) return;
-  const T s = sc ? (T)(*sc) : T(1);
-  auto u = [&](int m) -> T {
+struct LdPackDst {
+  const T* in;
+  const T* pre;
+  const double* sc;
+  int P;
+  __device__ T u(int m, T s) const {
     if (m == 0 || m == P) return T(0);
     const int mm = m < P ? m : 2 * P - m;
     T x = in[mm - 1] * s;
     if (pre) x *= pre[mm - 1];
     return m < P ? x : -x;
-  };
-  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < P; j += gridDim.x * blockDim.x) z[j] = mk(u(2 * j), u(2 * j + 1));
-}
+  }
+  __device__ cx<T> operator()(long, long j) const {
+    const T s = sc ? (T)(*sc) : T(1);
+    return mk(u(2 * (int)j, s), u(2 * (int)j + 1, s));
+  }
+};
 
 // DST value y_k (k = 1..n) from the P-point FFT Z of the packed odd extension.
 template <typename T>
@@ -131,72 +146,73 @@ __global__ void unpack_dst_kernel(const cx<T>* Z, const cx<T>* W, const T* post,
 }
 
 // Between the two DSTs of the preconditioner: y = DST(x) from Z, divide by F
-// (F_m = f[m - 1]), and pack the odd extension of y / F for the second DST.
+// (F_m = f[m - 1]), and the packed odd extension of y / F for the second DST.
 template <typename T>
-__global__ void unpack_f_pack_kernel(const cx<T>* Z, const cx<T>* W, const T* f, cx<T>* z2, int P,
-                                     const int* skip, const int* skip2) {
-  if (skip2f(skip, skip2)) return;
-  auto u = [&](int m) -> T {
+struct LdFRepack {
+  const cx<T>* Z;
+  const cx<T>* W;
+  const T* f;
+  int P;
+  __device__ T u(int m) const {
     if (m == 0 || m == P) return T(0);
     const int mm = m < P ? m : 2 * P - m;
     const T y = dst_value(Z, W, mm, P) / f[mm - 1];
     return m < P ? y : -y;
-  };
-  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < P; j += gridDim.x * blockDim.x) z2[j] = mk(u(2 * j), u(2 * j + 1));
-}
+  }
+  __device__ cx<T> operator()(long, long j) const { return mk(u(2 * (int)j), u(2 * (int)j + 1)); }
+};
 
 // Toeplitz packing: q_j = p_{2j} + i p_{2j+1}, p = (z_0..z_{n-1}, 0, ..., 0) of length 2P.
 template <typename T>
-__global__ void pack_toep_kernel(const T* zin, cx<T>* q, int n, int P, const int* skip, const int* skip2) {
-  if (skip2f(skip, skip2)) return;
-  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < P; j += gridDim.x * blockDim.x) {
-    const int a = 2 * j, b = 2 * j + 1;
-    q[j] = mk(a < n ? zin[a] : T(0), b < n ? zin[b] : T(0));
+struct LdPackToep {
+  const T* zin;
+  int n;
+  __device__ cx<T> operator()(long, long j) const {
+    const long a = 2 * j, b = 2 * j + 1;
+    return mk(a < n ? zin[a] : T(0), b < n ? zin[b] : T(0));
   }
-}
+};
 
 // Pair phase of the Toeplitz product: from Q (FFT of the packed zero-padded
-// input) form the half spectrum Ph, Y1 = lam Ph, Y2 = conj(lam) Ph, and the
-// conjugated packed inverse inputs conj(W1), conj(W2) at bins k and P - k.
+// input) the half spectrum Ph, Y1 = lam Ph (item 0) or Y2 = conj(lam) Ph
+// (item 1), and bin k of the conjugated packed inverse input conj(W1) or
+// conj(W2); bins k and P - k come from the same pair of Q bins.
 template <typename T>
-__global__ void pair_toep_kernel(const cx<T>* Q, const cx<T>* lam, const cx<T>* W, cx<T>* W1, cx<T>* W2, int P,
-                                 const int* skip, const int* skip2) {
-  if (skip2f(skip, skip2)) return;
-  const int H = P / 2;
-  auto winv = [&](cx<T> yk, cx<T> yn, cx<T> w) -> cx<T> {
+struct LdPairToep {
+  const cx<T>* Q;
+  const cx<T>* lam;
+  const cx<T>* W;
+  int P;
+  __device__ static cx<T> winv(cx<T> yk, cx<T> yn, cx<T> w) {
     const cx<T> s = scale(add(yk, conj(yn)), T(0.5));
     const cx<T> d = scale(sub(yk, conj(yn)), T(0.5));
     return add(s, mul_i(mul(conj(w), d)));
-  };
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k <= H; k += gridDim.x * blockDim.x) {
+  }
+  __device__ cx<T> operator()(long z, long jl) const {
+    const int k = (int)jl, H = P / 2;
+    const bool second = z != 0;
+    auto L = [&](cx<T> l) { return second ? conj(l) : l; };
     if (k == 0) {
       const cx<T> q0 = Q[0];
       const T p0 = q0.x + q0.y, pP = q0.x - q0.y;
-      const cx<T> l0 = lam[0], lP = lam[P], one = mk(T(1), T(0));
-      W1[0] = conj(winv(scale(l0, p0), scale(lP, pP), one));
-      W2[0] = conj(winv(scale(conj(l0), p0), scale(conj(lP), pP), one));
-    } else if (k == H) {
-      const cx<T> ph = conj(Q[H]);
-      const cx<T> w = mk(T(0), T(-1));
-      const cx<T> y1 = mul(lam[H], ph), y2 = mul(conj(lam[H]), ph);
-      W1[H] = conj(winv(y1, y1, w));
-      W2[H] = conj(winv(y2, y2, w));
-    } else {
-      const cx<T> qk = Q[k], qn = Q[P - k];
-      const cx<T> E = scale(add(qk, conj(qn)), T(0.5));
-      const cx<T> O = mul_mi(scale(sub(qk, conj(qn)), T(0.5)));
-      const cx<T> w = W[k];
-      const cx<T> wO = mul(w, O);
-      const cx<T> pk = add(E, wO), pn = conj(sub(E, wO));
-      const cx<T> lk = lam[k], ln = lam[P - k];
-      const cx<T> wn = mk(-w.x, w.y);
-      W1[k] = conj(winv(mul(lk, pk), mul(ln, pn), w));
-      W1[P - k] = conj(winv(mul(ln, pn), mul(lk, pk), wn));
-      W2[k] = conj(winv(mul(conj(lk), pk), mul(conj(ln), pn), w));
-      W2[P - k] = conj(winv(mul(conj(ln), pn), mul(conj(lk), pk), wn));
+      return conj(winv(scale(L(lam[0]), p0), scale(L(lam[P]), pP), mk(T(1), T(0))));
     }
+    if (k == H) {
+      const cx<T> y = mul(L(lam[H]), conj(Q[H]));
+      return conj(winv(y, y, mk(T(0), T(-1))));
+    }
+    const int kk = k < H ? k : P - k;   // the pair (kk, P - kk), 0 < kk < H
+    const cx<T> qk = Q[kk], qn = Q[P - kk];
+    const cx<T> E = scale(add(qk, conj(qn)), T(0.5));
+    const cx<T> O = mul_mi(scale(sub(qk, conj(qn)), T(0.5)));
+    const cx<T> w = W[kk];
+    const cx<T> wO = mul(w, O);
+    const cx<T> pk = add(E, wO), pn = conj(sub(E, wO));
+    const cx<T> yk = mul(L(lam[kk]), pk), yn = mul(L(lam[P - kk]), pn);
+    if (k < H) return conj(winv(yk, yn, w));
+    return conj(winv(yn, yk, mk(-w.x, w.y)));
   }
-}
+};
 
 // out_m = bscale * base_m + tscale * (cplus_m y1_m + cminus_m y2_m), where
 // y_{2j} = Re R_j / P and y_{2j+1} = -Im R_j / P for R = FFT(conj W).
