@@ -790,7 +790,8 @@ static void fourstep_k(LD in, cx<T>* out, long P, int npl, int batch, long ils, 
                        const cx<T>* Wsub, const cx<T>* Wbig, int apply, hipStream_t st, const int* skip,
                        const int* skip2) {
   constexpr int L = 1 << LOG;
-  constexpr int B = L >= 512 ? 1 : 512 / L;
+  constexpr int B = fourstep_lines(L);
+  constexpr int EPT = fourstep_ept(L);
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&fourstep_kernel<T, LOG, CIN, COUT, LD>),
@@ -799,7 +800,7 @@ static void fourstep_k(LD in, cx<T>* out, long P, int npl, int batch, long ils, 
   }
   const size_t lds = ((size_t)B * line_stride(L) + (size_t)B * L) * sizeof(cx<T>);
   const long lines = (long)batch * npl;   // B divides npl (both powers of two, npl >= 64 >= B)
-  hipLaunchKernelGGL((fourstep_kernel<T, LOG, CIN, COUT, LD>), dim3((unsigned)(lines / B)), dim3(B * L / 8), lds, st, in,
+  hipLaunchKernelGGL((fourstep_kernel<T, LOG, CIN, COUT, LD>), dim3((unsigned)(lines / B)), dim3(B * L / EPT), lds, st, in,
                      out, P, npl, ils, ies, ols, oes, Wsub, Wbig, apply, skip, skip2);
 }
 

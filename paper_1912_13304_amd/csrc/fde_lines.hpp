@@ -185,7 +185,9 @@ template <typename T, int EPT, int LOGP, int LOGLS>
 __device__ __forceinline__ void fft_lines_ct(cx<T>* buf, int LS, const cx<T>* tw) {
   if constexpr (LOGLS < LOGP) {
     constexpr int REM = LOGP - LOGLS;
-    constexpr int LOGR = REM >= 3 ? 3 : REM;
+    constexpr int LOGE = ilog2c(EPT);   // a pass's radix is at most EPT
+    constexpr int LOGR0 = REM >= 3 ? 3 : REM;
+    constexpr int LOGR = LOGR0 < LOGE ? LOGR0 : LOGE;
     fft_pass<T, EPT, (1 << LOGR)>(buf, LS, LOGP - LOGR, 1 << LOGLS, LOGR, tw, 1 << LOGP, LOGP + 1 - LOGLS - LOGR);
     fft_lines_ct<T, EPT, LOGP, LOGLS + LOGR>(buf, LS, tw);
   }
