@@ -179,6 +179,7 @@ static size_t plan_bytes_impl(const fde_params* p) {
   size_t b = 0;
   const int ncoef = p->dim == 2 ? 4 : 2;
   b += (size_t)N * (ncoef + 1) * (8 + 4);       // coefficients and D^{-1}, both precisions
+  if (p->dim == 2 && n2 + 1 > 2048) b += (size_t)N * 2 * (8 + 4);   // e+- transposed (y passes on the transpose)
   b += (size_t)(n1 + n2 + 1) * (8 + 4);         // symbol samples
   b += (size_t)4 * (2 * (n1 + 1) + 2 * (n2 + 1)) * (16 + 8);  // twiddles and eigenvalues
   if (p->solver == FDE_S_PCG) b += (size_t)N * 8 * 6;
@@ -414,7 +415,7 @@ static fde_status assemble_impl(const fde_params* p, const double* dp, const dou
   pl->c64.dm = d64[1];
   pl->c64.ep = d64[2];
   pl->c64.em = d64[3];
-  if (p->dim == 2) {
+  if (p->dim == 2 && !pl->use_cols) {   // e+- transposed for the y passes that run on the transpose
     TRY(dalloc(pl, &pl->c64.ept, N));
     TRY(dalloc(pl, &pl->c64.emt, N));
     TRY(dalloc(pl, &pl->c32.ept, N));
@@ -728,8 +729,9 @@ const Consts<double>& consts<double>(fde_plan pl) { return pl->c64; }
 template <>
 const Consts<float>& consts<float>(fde_plan pl) { return pl->c32; }
 
-// Toeplitz-type LineArgs.  ydir: lines along y, i.e. rows of the transposed
-// (n1, n2) array, with the transposed e+- coefficients.
+// Toeplitz-type LineArgs.  ydir: lines along y, with e+- in the original
+// layout (columns read in place) or transposed (rows of the transposed
+// (n1, n2) array, for the sizes that keep the transposes).
 template <typename T>
 static LineArgs<T> toep_args(fde_plan pl, bool ydir, const int* skip, const int* skip2) {
   const Consts<T>& c = consts<T>(pl);
@@ -755,7 +757,8 @@ static void transpose(fde_plan pl, const T* in, T* out, int rows, int cols, cons
 }
 
 // y-direction part added to an x-direction part: y = xpart + tscale * kappa *
-// (E+ (T_y (x) I) + E- (T_y^T (x) I)) x, computed on the transpose of x.
+// (E+ (T_y (x) I) + E- (T_y^T (x) I)) x, on the columns of x in place, or on
+// its transpose.
 template <typename T>
 static void add_y_part(fde_plan pl, const T* x, const T* xpart, T* y, T tscale, hipStream_t st, const int* skip,
                        const int* skip2) {

@@ -16,10 +16,13 @@
 //    FFTs (each real 2P-point sequence is recovered from a P-point complex one).
 //
 // The FFT is a Stockham autosort FFT (radix 8, with one radix-4 or radix-2
-// pass when log2 P is not a multiple of 3).  Each workgroup transforms B lines
-// at once; every thread owns EPT = 8 elements in the elementwise phases and
-// EPT/R butterflies in a radix-R pass, so blockDim = B*P/8.  Twiddles come from
-// a host-computed float64 table W2[m] = exp(-2 pi i m/(2P)), m < 2P.
+// pass when log2 P is not a multiple of 3) in a padded LDS layout.  Each
+// workgroup transforms B lines at once (rows: one line from P = 512 up;
+// columns: up to four neighbouring columns); every thread owns EPT = 8
+// elements in the elementwise phases and EPT/R butterflies in a radix-R pass,
+// so blockDim = B*P/8.  Twiddles come from a host-computed float64 table
+// W2[m] = exp(-2 pi i m/(2P)), m < 2P; a butterfly reads one and forms the
+// powers it needs by products.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -359,3 +359,27 @@ def test_plan_buffers_reused_and_released():
             assert r[2] == runs[0][2]
             assert np.array_equal(r[1], runs[0][1])
         assert relerr(s.matvec(runs[0][1]), b) <= 1e-8 * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("case", ["2d-1023-fp64", "2d-1023-mixed", "2d-15x4095", "1d-65535-fp64",
+                                  "1d-65535-mixed", "1d-1023-pcg"])
+def test_plan_bytes_matches_device_allocation(case):
+    """fde_plan_bytes (the admission figure of the server) agrees with what
+    assembly takes from the device, measured with the memory cache empty
+    (to within a few percent on the large plans)."""
+    fde = need_gpu()
+    p = {"2d-1023-fp64": lambda: prob2d(1023, 1023), "2d-1023-mixed": lambda: prob2d(1023, 1023),
+         "2d-15x4095": lambda: prob2d(15, 4095), "1d-65535-fp64": lambda: prob1d(65535),
+         "1d-65535-mixed": lambda: prob1d(65535), "1d-1023-pcg": lambda: fi.constant_1d(n=1023)}[case]()
+    kw = dict(precision=fde.MIXED) if case.endswith("mixed") else {}
+    fde.fde_release_cache()
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    with fde.Plan(p, **kw) as plan:
+        torch.cuda.synchronize()
+        used = free0 - torch.cuda.mem_get_info()[0]
+        claimed = fde.fde_plan_bytes(plan.params)
+    fde.fde_release_cache()
+    # 8 MB for the runtime's allocation granularity over a plan's few dozen buffers
+    assert claimed >= 0.95 * used - (8 << 20), (claimed, used)
+    assert claimed <= 1.25 * used + (8 << 20), (claimed, used)
