@@ -90,6 +90,31 @@ def model_bytes_1d(n, iters, inner, m, kin, mixed):
     return tot
 
 
+def model_bytes_2d(N, outer, inner_total, m, mixed):
+    """Algorithmic bytes of one 2D FGMRES(m) solve of the plan path (every
+    vector operand of every kernel read or written once, D on the left), in
+    units of N:
+      float64 step j (k = j + 1 basis vectors): row DST 24, column DST/F/DST
+      16, row DST + z + row Toeplitz 40, column Toeplitz with base 40, CGS2
+      (3k + 5) * 8;
+      mixed outer step j: cast of v 12, inner norm 4, per inner step i (float32,
+      k = i + 1): tau + matvec 60 and single-pass Gram-Schmidt (2k + 3) * 4;
+      the inner update 4 (kin + 1), the float32 tau solve 28, the cast back 12,
+      the float64 matvec 72 and CGS2 (3(j + 1) + 5) * 8."""
+    tot = 0.0
+    kin = inner_total / outer if (mixed and outer) else 0.0
+    for t in range(outer):
+        j = t % m
+        cgs64 = (3 * (j + 1) + 5) * 8
+        if mixed:
+            ki = int(round(kin))
+            inner = sum(60 + (2 * (i + 1) + 3) * 4 for i in range(ki))
+            tot += 12 + 4 + inner + 4 * (ki + 1) + 28 + 12 + 72 + cgs64
+        else:
+            tot += 24 + 16 + 40 + 40 + cgs64
+    return tot * N
+
+
 def batched_leg(args, fi, fde, torch, np):
     """Many independent uneven 1D solves in one persistent launch per time
     step (graph replayed per step), launch configuration picked by the tuner;
@@ -427,28 +452,43 @@ def main():
                                             launches=v["launches"]) for k, v in shares.items()},
             dominant=dict(cls=dom, ms=probe_tot[0], launches=probe_tot[1], bytes=probe_tot[2]),
         )
+        # whole-iteration roofline: modelled algorithmic bytes of all the
+        # solves of the timed jobs over their wall time
+        mb = sum(model_bytes_2d(N, i["iters"], i["inner_iters"], 30, name == "mixed")
+                 for inf in all_infos for i in inf)
+        results[name]["iteration_roofline"] = dict(
+            model_bytes_per_solve=mb / solves, GBps=mb / dt / 1e9, frac=mb / dt / 1e9 / PEAK_HBM_GBS,
+            peak=PEAK_HBM_GBS, note="all kernels of the solve; bytes from model_bytes_2d, time = wall time of "
+                                    "the timed jobs (assembly and right-hand sides included)")
         log(f"[bench] {name}: {results[name]['solves_per_s']:.1f} solves/s, "
-            f"{results[name]['ms_per_solve']:.2f} ms/solve, {results[name]['iters_per_solve']:.1f} it/solve")
+            f"{results[name]['ms_per_solve']:.2f} ms/solve, {results[name]['iters_per_solve']:.1f} it/solve, "
+            f"whole-iteration {results[name]['iteration_roofline']['GBps']:.0f} GB/s")
 
     # served leg: Poisson arrivals of mixed 1D / 2D time-stepping requests,
-    # continuous batching over slots x streams; each request in its faster
-    # form (mixed for 2D, float64 for 1D)
+    # continuous batching over slots x streams, every request in the mixed
+    # form; beside it the same stream with each request in its faster form
+    # (mixed for 2D, float64 for 1D)
     served = None
     if args.serve_count > 0:
         from paper_1912_13304_amd import serve
+        mix = ("70% 1D n log-uniform in [1023, 65535] rounded to 2^k-1, 30% 2D n in {127,255,511,1023}; "
+               "5-50 steps; alpha ~ U(1.1,1.9); tol 1e-8; ")
         arr = fi.served_stream(args.serve_rate, args.serve_count, seed=5, n1d=(1023, 65535))
-        serve.serve_stream(arr[:4], slots=args.serve_slots, precision=serve.AUTO, inner_steps=args.inner)  # warm
-        res, wall = serve.serve_stream(arr, slots=args.serve_slots, precision=serve.AUTO, inner_steps=args.inner)
+        serve.serve_stream(arr[:4], slots=args.serve_slots, precision=fde.MIXED, inner_steps=args.inner)  # warm
+        res, wall = serve.serve_stream(arr, slots=args.serve_slots, precision=fde.MIXED, inner_steps=args.inner)
         served = serve.latency_stats(res)
-        served.update(rate_req_per_s=args.serve_rate, slots=args.serve_slots,
-                      mix="70% 1D n log-uniform in [1023, 65535] rounded to 2^k-1, 30% 2D n in "
-                          "{127,255,511,1023}; 5-50 steps; alpha ~ U(1.1,1.9); tol 1e-8; mixed precision "
-                          "for 2D requests, float64 for 1D requests")
+        served.update(rate_req_per_s=args.serve_rate, slots=args.serve_slots, mix=mix + "mixed precision")
         log(f"[bench] served: {served}")
+        res, wall = serve.serve_stream(arr, slots=args.serve_slots, precision=serve.AUTO, inner_steps=args.inner)
+        auto = serve.latency_stats(res)
+        auto.update(rate_req_per_s=args.serve_rate, slots=args.serve_slots,
+                    mix=mix + "mixed precision for 2D requests, float64 for 1D requests")
+        served["per_request_precision"] = auto
+        log(f"[bench] served, per-request precision: {auto}")
         sweep = []
         for r in [float(x) for x in args.serve_sweep.split(",") if x.strip()]:
             arr = fi.served_stream(r, args.serve_count, seed=5, n1d=(1023, 65535))
-            res, wall = serve.serve_stream(arr, slots=args.serve_slots, precision=serve.AUTO, inner_steps=args.inner)
+            res, wall = serve.serve_stream(arr, slots=args.serve_slots, precision=fde.MIXED, inner_steps=args.inner)
             st = serve.latency_stats(res)
             st.update(rate_req_per_s=r)
             sweep.append(st)
