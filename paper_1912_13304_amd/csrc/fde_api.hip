@@ -682,7 +682,7 @@ static void launch_line(const Dir& d, LineArgs<T> a, hipStream_t st) {
   a.es = d.es;
   a.ntiles = (d.nlines + d.B - 1) / d.B;
   const int nth = std::max(1, d.B * d.P / 8);
-  const size_t lds = ((size_t)d.B * a.LS + 2 * d.B + (size_t)d.B * d.P) * sizeof(cx<T>);
+  const size_t lds = ((size_t)d.B * a.LS + 2 * d.B + (size_t)d.P) * sizeof(cx<T>);
   const int grid = 8 * ((a.ntiles + 7) / 8);
   // algorithmic bytes: every vector operand read or written once
   const int nvec = (a.in != nullptr) + (a.pre != nullptr) + (a.post != nullptr) + (a.zout != nullptr) +

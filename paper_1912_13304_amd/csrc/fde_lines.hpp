@@ -287,8 +287,11 @@ __global__ void __launch_bounds__(512) line_kernel(LineArgs<T> a) {
   const int tid = threadIdx.x;
   const int n = a.n;
   const int line0 = tile * B;
-  // LDS: B line buffers, 2B side entries, B*P twiddle slots (the first P used)
+  // LDS: B line buffers, 2B side entries, P twiddle slots
   cx<T>* tw = buf + B * LS + 2 * B;
+  // twiddle loads per thread: ceil(P / nth) = ceil(EPT / B) (all of them for
+  // the generic form)
+  constexpr int TWK = LOGP > 0 ? (EPT / CB > 1 ? EPT / CB : 1) : EPT;
 
   int li[EPT], mi[EPT];
   int gi[EPT];   // element offsets (N < 2^31); 0 for padding/out-of-range slots
@@ -314,9 +317,9 @@ __global__ void __launch_bounds__(512) line_kernel(LineArgs<T> a) {
   // a valid offset) and before any use, so that all loads are in flight
   // together and their latency overlaps the transforms below.
   T xpre[EPT], xpost[EPT], xcp[EPT], xcm[EPT], xb[EPT], xf[EPT];
-  T twr[EPT], twi[EPT];
+  T twr[TWK], twi[TWK];
 #pragma unroll
-  for (int k = 0; k < EPT; ++k) {
+  for (int k = 0; k < TWK; ++k) {
     const cx<T> t = a.W2[(tid + k * nth) & (P - 1)];
     twr[k] = t.x;
     twi[k] = t.y;
@@ -340,7 +343,8 @@ __global__ void __launch_bounds__(512) line_kernel(LineArgs<T> a) {
   // their load) with the loads above
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-  for (int k = 0; k < EPT; ++k) tw[tid + k * nth] = mk(twr[k], twi[k]);   // B*P >= P slots
+  for (int k = 0; k < TWK; ++k)
+    if (tid + k * nth < P) tw[tid + k * nth] = mk(twr[k], twi[k]);
   {
     const T sc = a.sc ? (T)(*a.sc) : T(1);
 #pragma unroll
