@@ -541,12 +541,26 @@ def main():
         # oracle's FGMRES) and mixed form (a different Krylov path to the same
         # tolerance), each with its true residual recomputed by the oracle
         parity = {"oracle_iters": io["iters"], "tol": prob.tol}
+        firsts = {}
         for fname, fkw in (("fp64", dict(precision=fde.FP64)),
                            ("mixed", dict(precision=fde.MIXED, inner_steps=args.inner))):
             _, _, first = job(fkw, keep_first=True)
+            firsts[fname] = first
             parity[f"{fname}_first_solve_rel_diff"] = float(np.linalg.norm(first - xo) / np.linalg.norm(xo))
             parity[f"{fname}_first_solve_true_relres"] = float(np.linalg.norm(bh - s.matvec(first)) /
                                                               np.linalg.norm(bh))
+        # the error of each form itself: against the same step solved to 1e-12
+        # by the FP64 path (whose iterates mirror the oracle's)
+        tight = fde.fde_assemble(fde.params_for(prob, precision=fde.FP64, tol=1e-12), *coef)
+        fde.fde_rhs(tight, u0, None, b)
+        xt = u0.clone()
+        fde.fde_solve(tight, b, xt, allow_notconv=True)   # its true residual is reported
+        fde.fde_destroy(tight)
+        xt = xt.cpu().numpy()
+        parity["tight_reference_true_relres"] = float(np.linalg.norm(bh - s.matvec(xt)) / np.linalg.norm(bh))
+        for fname, first in firsts.items():
+            parity[f"{fname}_first_solve_error_vs_tight"] = float(np.linalg.norm(first - xt) / np.linalg.norm(xt))
+        parity["oracle_error_vs_tight"] = float(np.linalg.norm(xo - xt) / np.linalg.norm(xt))
         log(f"[bench] oracle {tc:.1f} s, parity {parity}")
 
     out = {
