@@ -279,7 +279,9 @@ def one_d_legs(args, fi, fde, torch, np):
     n = 1023, alpha = 1.5) solved by PCG with the Case I preconditioner to
     1e-10, time-to-tol per solve; (b) 20 implicit steps of the 1D
     variable-coefficient problem at n = 65535 for alpha = 1.2, 1.5, 1.8,
-    float64 and mixed forms, solves per second."""
+    float64 form and the float32-preconditioner form (float32 tau inside the
+    float64 FGMRES, no inner Krylov: inner_steps = 0, the faster mixed form on
+    long 1D lines), solves per second."""
     T = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda").reshape(-1).contiguous()
     out = {}
     p = fi.constant_1d()
@@ -298,7 +300,7 @@ def one_d_legs(args, fi, fde, torch, np):
     jobs = {}
     for alpha in (1.2, 1.5, 1.8):
         p = fi.variable_1d(n=65535, alpha=alpha, steps=20)
-        for name, kw in (("fp64", dict(precision=fde.FP64)), ("mixed", dict(precision=fde.MIXED, inner_steps=args.inner))):
+        for name, kw in (("fp64", dict(precision=fde.FP64)), ("mixed", dict(precision=fde.MIXED, inner_steps=0))):
             with fde.Plan(p, **kw) as plan:
                 u = T(p.u0)
                 bb = torch.empty_like(u)
@@ -474,10 +476,12 @@ def main():
         mix = ("70% 1D n log-uniform in [1023, 65535] rounded to 2^k-1, 30% 2D n in {127,255,511,1023}; "
                "5-50 steps; alpha ~ U(1.1,1.9); tol 1e-8; ")
         arr = fi.served_stream(args.serve_rate, args.serve_count, seed=5, n1d=(1023, 65535))
-        serve.serve_stream(arr[:4], slots=args.serve_slots, precision=fde.MIXED, inner_steps=args.inner)  # warm
-        res, wall = serve.serve_stream(arr, slots=args.serve_slots, precision=fde.MIXED, inner_steps=args.inner)
+        serve.serve_stream(arr[:4], slots=args.serve_slots, precision=fde.MIXED, inner_steps=serve.AUTO)  # warm
+        res, wall = serve.serve_stream(arr, slots=args.serve_slots, precision=fde.MIXED, inner_steps=serve.AUTO)
         served = serve.latency_stats(res)
-        served.update(rate_req_per_s=args.serve_rate, slots=args.serve_slots, mix=mix + "mixed precision")
+        served.update(rate_req_per_s=args.serve_rate, slots=args.serve_slots,
+                      mix=mix + f"mixed precision (float32 inner GMRES({serve.INNER_2D}) for 2D requests, float32 "
+                                f"preconditioner without inner steps for 1D requests)")
         log(f"[bench] served: {served}")
         res, wall = serve.serve_stream(arr, slots=args.serve_slots, precision=serve.AUTO, inner_steps=args.inner)
         auto = serve.latency_stats(res)
@@ -488,7 +492,7 @@ def main():
         sweep = []
         for r in [float(x) for x in args.serve_sweep.split(",") if x.strip()]:
             arr = fi.served_stream(r, args.serve_count, seed=5, n1d=(1023, 65535))
-            res, wall = serve.serve_stream(arr, slots=args.serve_slots, precision=fde.MIXED, inner_steps=args.inner)
+            res, wall = serve.serve_stream(arr, slots=args.serve_slots, precision=fde.MIXED, inner_steps=serve.AUTO)
             st = serve.latency_stats(res)
             st.update(rate_req_per_s=r)
             sweep.append(st)

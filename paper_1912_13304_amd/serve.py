@@ -44,22 +44,26 @@ class Result:
 
 
 AUTO = "auto"
+INNER_2D = 16   # float32 inner GMRES steps of a 2D mixed request
 
 
 def request_kw(problem, solve_kw: dict) -> dict:
-    """Solver options of one request.  precision="auto" picks the faster
-    form per request class, as measured on the benchmark's workloads: the
-    mixed form (float32 inner GMRES) for 2D requests, where it moves half
-    the bytes per inner step, and float64 for 1D requests, whose iterations
-    are bound by kernel launches rather than bytes, so that the inner
-    iterations of the mixed form only add time."""
+    """Solver options of one request, with the per-class choices measured on
+    the benchmark's workloads:
+      precision="auto": the mixed form for 2D requests, where its float32
+        inner steps move half the bytes, and float64 for 1D requests, whose
+        long-line iterations are bound by kernel launches rather than bytes;
+      inner_steps="auto" (mixed requests): GMRES(INNER_2D) in float32 for 2D,
+        and no inner steps (the float32 preconditioner alone inside the
+        float64 FGMRES) for 1D, where the float32 inner iterations do not pay
+        for themselves."""
     kw = dict(solve_kw)
     if kw.get("precision") == AUTO:
-        if problem.dim == 2:
-            kw["precision"] = fde.MIXED
-        else:
-            kw["precision"] = fde.FP64
-            kw.pop("inner_steps", None)
+        kw["precision"] = fde.MIXED if problem.dim == 2 else fde.FP64
+    if kw.get("precision") != fde.MIXED:
+        kw.pop("inner_steps", None)
+    elif kw.get("inner_steps") == AUTO:
+        kw["inner_steps"] = INNER_2D if problem.dim == 2 else 0
     return kw
 
 

@@ -14,12 +14,14 @@ def small_stream(rate=2000.0, count=8, seed=21):
     return fi.served_stream(rate, count, seed=seed, n1d=(255, 4095), n2d=(63, 127, 255), steps=(2, 5))
 
 
-@pytest.mark.parametrize("precision", [0, 1, "auto"])
-def test_alone_equals_mix(precision):
+@pytest.mark.parametrize("precision,inner", [(0, None), (1, None), ("auto", None), (1, "auto")])
+def test_alone_equals_mix(precision, inner):
     fde = need_gpu()
     from paper_1912_13304_amd import serve
     arr = small_stream()
     kw = dict(precision=precision)
+    if inner is not None:
+        kw["inner_steps"] = inner
     results, wall = serve.serve_stream(arr, slots=4, keep_state=True, **kw)
     assert len(results) == len(arr)
     by_name = {r.name: r for r in results}

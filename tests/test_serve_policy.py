@@ -16,3 +16,15 @@ def test_auto_precision_by_request_class():
     for p in (p1, p2):
         assert serve.request_kw(p, dict(precision=fde.MIXED))["precision"] == fde.MIXED
         fde.params_for(p, **serve.request_kw(p, kw))   # valid parameter sets
+
+
+def test_auto_inner_steps_by_request_class():
+    p1 = fi.variable_1d(n=1023, steps=2)
+    p2 = fi.variable_2d(n=63, steps=2)
+    kw = dict(precision=fde.MIXED, inner_steps=serve.AUTO)
+    assert serve.request_kw(p1, kw) == dict(precision=fde.MIXED, inner_steps=0)
+    assert serve.request_kw(p2, kw) == dict(precision=fde.MIXED, inner_steps=serve.INNER_2D)
+    # float64 requests take no inner length
+    assert serve.request_kw(p1, dict(precision=serve.AUTO, inner_steps=serve.AUTO)) == dict(precision=fde.FP64)
+    for p in (p1, p2):
+        fde.params_for(p, **serve.request_kw(p, kw))
