@@ -78,12 +78,13 @@ def model_bytes_1d(n, iters, inner, m, kin, mixed):
     tau 24n + matvec 32n + CGS2 (32j + 80)n + normalisation 16n in float64;
     the mixed form replaces the tau solve by the cast of v (12n), kin float32
     inner steps (tau 12n, matvec 16n, CGS2 (16i + 40)n each), the inner update
-    (4(kin+1)n), the float32 tau solve (12n) and the cast back (12n)."""
+    (4(kin+1)n, none when kin = 0), the float32 tau solve (12n) and the cast
+    back (12n)."""
     tot = 0.0
     for t in range(iters):
         j = t % m
         if mixed:
-            inner_b = sum(12 + 16 + 16 * i + 40 for i in range(kin)) + 4 * (kin + 1) + 12 + 12 + 12
+            inner_b = sum(12 + 16 + 16 * i + 40 for i in range(kin)) + (4 * (kin + 1) if kin else 0) + 12 + 12 + 12
             tot += (32 + 32 * j + 80 + 16 + inner_b) * n
         else:
             tot += (152 + 32 * j) * n
@@ -122,8 +123,11 @@ def batched_leg(args, fi, fde, torch, np):
     probs = fi.batched_1d(count=args.batch_count, seed=4, steps=args.batch_steps)
     out = {"instances": len(probs), "unknowns": int(sum(p.n[0] for p in probs)),
            "workload": f"{len(probs)} 1D instances, n log-uniform in [255, 16383] (any n), alpha ~ U(1.1,1.9), "
-                       "Example-1 coefficients x U(0.5,2), dt = h, FGMRES(30)+P_F to 1e-8, x0 = u^(m-1)"}
-    forms = {"mixed": dict(precision=fde.MIXED, inner_steps=args.inner), "fp64": dict(precision=fde.FP64)}
+                       "Example-1 coefficients x U(0.5,2), dt = h, FGMRES(30)+P_F to 1e-8, x0 = u^(m-1); "
+                       f"mixed form: float32 P_F inside the float64 FGMRES, {args.batch_inner} inner steps"}
+    # mixed: the float32 preconditioner inside the float64 FGMRES, no inner
+    # steps (faster than GMRES(16) inner solves on these 1D lines)
+    forms = {"mixed": dict(precision=fde.MIXED, inner_steps=args.batch_inner), "fp64": dict(precision=fde.FP64)}
     cfg = None
     for name, kw in forms.items():
         bt = fde.Batch(probs, **kw)
@@ -143,7 +147,7 @@ def batched_leg(args, fi, fde, torch, np):
         its = [i.iters for st in infos for i in st]
         inner = [i.inner_iters for st in infos for i in st]
         mixed = name == "mixed"
-        byt = sum(model_bytes_1d(p.n[0], i.iters, 0, 30, args.inner if mixed else 0, mixed)
+        byt = sum(model_bytes_1d(p.n[0], i.iters, 0, 30, args.batch_inner if mixed else 0, mixed)
                   for st in infos for p, i in zip(probs, st))
         out[name] = dict(inst_steps_per_s=len(probs) * args.batch_steps / dt, ms_per_step=1e3 * dt / args.batch_steps,
                          modelled_GBps=byt / dt / 1e9, iters_mean=float(np.mean(its)), iters_max=int(max(its)),
@@ -326,7 +330,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=1023)
     ap.add_argument("--tsteps", type=int, default=10)
-    ap.add_argument("--inner", type=int, default=16)
+    ap.add_argument("--inner", type=int, default=16, help="float32 inner GMRES steps of the 2D mixed form")
+    ap.add_argument("--batch-inner", type=int, default=0, help="inner steps of the batched mixed form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--quick", action="store_true",

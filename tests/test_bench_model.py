@@ -13,3 +13,11 @@ def test_model_bytes_2d_per_step():
     inner = sum(60 + (2 * k + 3) * 4 for k in range(1, 17))
     assert bench.model_bytes_2d(1, 1, 16, 30, True) == 24 + 4 + inner + 68 + 28 + 72 + 64
     assert bench.model_bytes_2d(1000, 1, 16, 30, True) == 1000 * bench.model_bytes_2d(1, 1, 16, 30, True)
+
+
+def test_model_bytes_1d_per_step():
+    # float64 step j: tau 24 + matvec 32 + CGS2 (32j + 80) + normalisation 16
+    assert bench.model_bytes_1d(1, 1, 0, 30, 0, False) == 152
+    assert bench.model_bytes_1d(1, 2, 0, 30, 0, False) == 152 + 184
+    # float32 preconditioner alone (no inner steps): casts and tau 36 instead of tau 24
+    assert bench.model_bytes_1d(1, 1, 0, 30, 0, True) == 32 + 80 + 16 + 36
