@@ -657,7 +657,7 @@ struct ProbePlanScope {
 };
 
 template <typename T, bool COLS, int FL, int LOGP>
-static void launch_line_k(const Dir& d, const LineArgs<T>& a, int grid, int nth, size_t lds, hipStream_t st) {
+static void launch_line_k(const LineArgs<T>& a, int grid, int nth, size_t lds, hipStream_t st) {
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&line_kernel<T, COLS, FL, LOGP>),
@@ -692,30 +692,30 @@ static void launch_line(const Dir& d, LineArgs<T> a, hipStream_t st) {
                 (sizeof(T) == 8 ? FDE_PROBE_LINE64_VARIANT : FDE_PROBE_LINE32_VARIANT) + FL);
   if constexpr (COLS) {
     switch (d.logP) {   // cols_per_tile(P) >= 2: P <= 2048
-      case 3: launch_line_k<T, true, FL, 3>(d, a, grid, nth, lds, st); break;
-      case 4: launch_line_k<T, true, FL, 4>(d, a, grid, nth, lds, st); break;
-      case 5: launch_line_k<T, true, FL, 5>(d, a, grid, nth, lds, st); break;
-      case 6: launch_line_k<T, true, FL, 6>(d, a, grid, nth, lds, st); break;
-      case 7: launch_line_k<T, true, FL, 7>(d, a, grid, nth, lds, st); break;
-      case 8: launch_line_k<T, true, FL, 8>(d, a, grid, nth, lds, st); break;
-      case 9: launch_line_k<T, true, FL, 9>(d, a, grid, nth, lds, st); break;
-      case 10: launch_line_k<T, true, FL, 10>(d, a, grid, nth, lds, st); break;
-      case 11: launch_line_k<T, true, FL, 11>(d, a, grid, nth, lds, st); break;
-      default: launch_line_k<T, true, FL, 0>(d, a, grid, nth, lds, st); break;
+      case 3: launch_line_k<T, true, FL, 3>(a, grid, nth, lds, st); break;
+      case 4: launch_line_k<T, true, FL, 4>(a, grid, nth, lds, st); break;
+      case 5: launch_line_k<T, true, FL, 5>(a, grid, nth, lds, st); break;
+      case 6: launch_line_k<T, true, FL, 6>(a, grid, nth, lds, st); break;
+      case 7: launch_line_k<T, true, FL, 7>(a, grid, nth, lds, st); break;
+      case 8: launch_line_k<T, true, FL, 8>(a, grid, nth, lds, st); break;
+      case 9: launch_line_k<T, true, FL, 9>(a, grid, nth, lds, st); break;
+      case 10: launch_line_k<T, true, FL, 10>(a, grid, nth, lds, st); break;
+      case 11: launch_line_k<T, true, FL, 11>(a, grid, nth, lds, st); break;
+      default: launch_line_k<T, true, FL, 0>(a, grid, nth, lds, st); break;
     }
   } else {
     switch (d.logP) {
-      case 3: launch_line_k<T, false, FL, 3>(d, a, grid, nth, lds, st); break;
-      case 4: launch_line_k<T, false, FL, 4>(d, a, grid, nth, lds, st); break;
-      case 5: launch_line_k<T, false, FL, 5>(d, a, grid, nth, lds, st); break;
-      case 6: launch_line_k<T, false, FL, 6>(d, a, grid, nth, lds, st); break;
-      case 7: launch_line_k<T, false, FL, 7>(d, a, grid, nth, lds, st); break;
-      case 8: launch_line_k<T, false, FL, 8>(d, a, grid, nth, lds, st); break;
-      case 9: launch_line_k<T, false, FL, 9>(d, a, grid, nth, lds, st); break;
-      case 10: launch_line_k<T, false, FL, 10>(d, a, grid, nth, lds, st); break;
-      case 11: launch_line_k<T, false, FL, 11>(d, a, grid, nth, lds, st); break;
-      case 12: launch_line_k<T, false, FL, 12>(d, a, grid, nth, lds, st); break;
-      default: launch_line_k<T, false, FL, 0>(d, a, grid, nth, lds, st); break;
+      case 3: launch_line_k<T, false, FL, 3>(a, grid, nth, lds, st); break;
+      case 4: launch_line_k<T, false, FL, 4>(a, grid, nth, lds, st); break;
+      case 5: launch_line_k<T, false, FL, 5>(a, grid, nth, lds, st); break;
+      case 6: launch_line_k<T, false, FL, 6>(a, grid, nth, lds, st); break;
+      case 7: launch_line_k<T, false, FL, 7>(a, grid, nth, lds, st); break;
+      case 8: launch_line_k<T, false, FL, 8>(a, grid, nth, lds, st); break;
+      case 9: launch_line_k<T, false, FL, 9>(a, grid, nth, lds, st); break;
+      case 10: launch_line_k<T, false, FL, 10>(a, grid, nth, lds, st); break;
+      case 11: launch_line_k<T, false, FL, 11>(a, grid, nth, lds, st); break;
+      case 12: launch_line_k<T, false, FL, 12>(a, grid, nth, lds, st); break;
+      default: launch_line_k<T, false, FL, 0>(a, grid, nth, lds, st); break;
     }
   }
 }
@@ -747,7 +747,7 @@ static LineArgs<T> toep_args(fde_plan pl, bool ydir, const int* skip, const int*
 
 // out (cols x rows) = in^T (+ addend)
 template <typename T>
-static void transpose(fde_plan pl, const T* in, T* out, int rows, int cols, const T* addend, hipStream_t st,
+static void transpose(const T* in, T* out, int rows, int cols, const T* addend, hipStream_t st,
                       const int* skip, const int* skip2) {
   const dim3 g((cols + 31) / 32, (rows + 31) / 32);
   if (addend)
@@ -775,14 +775,14 @@ static void add_y_part(fde_plan pl, const T* x, const T* xpart, T* y, T tscale, 
   }
   T* xt = pl->tmp<T>(1);
   T* yt = pl->tmp<T>(2);
-  transpose<T>(pl, x, xt, pl->n2, pl->n1, nullptr, st, skip, skip2);
+  transpose<T>(x, xt, pl->n2, pl->n1, nullptr, st, skip, skip2);
   LineArgs<T> q = toep_args<T>(pl, true, skip, skip2);
   q.in = xt;
   q.bscale = T(0);
   q.tscale = tscale * (T)pl->kappa;
   q.out = yt;
   launch_line<T, LF_TOEP>(pl->trows, q, st);
-  transpose<T>(pl, yt, y, pl->n1, pl->n2, xpart, st, skip, skip2);
+  transpose<T>(yt, y, pl->n1, pl->n2, xpart, st, skip, skip2);
 }
 
 // ---------------------------------------------------------------------------
@@ -917,11 +917,11 @@ static void y_dst_f_dst(fde_plan pl, T* t, T* out, hipStream_t st, const int* sk
     launch_line<T, LF_DST1 | LF_FDST2, true>(pl->ycols, b, st);
     return;
   }
-  transpose<T>(pl, t, out, pl->n2, pl->n1, nullptr, st, skip, skip2);
+  transpose<T>(t, out, pl->n2, pl->n1, nullptr, st, skip, skip2);
   b.in = out;
   b.out = t;
   launch_line<T, LF_DST1 | LF_FDST2>(pl->trows, b, st);
-  transpose<T>(pl, t, out, pl->n1, pl->n2, nullptr, st, skip, skip2);
+  transpose<T>(t, out, pl->n1, pl->n2, nullptr, st, skip, skip2);
 }
 
 template <typename T>

@@ -236,8 +236,8 @@ __device__ inline void publish_or_finish(double* tot, int nq, double* part, KSta
 // FK_H: one workgroup per Gram-Schmidt coefficient, each stores its own h_q
 // and c_q.  FK_NORM / FK_DOT: a single value, then the scalar epilogue.
 __global__ void __launch_bounds__(RED_THREADS)
-finalize_kernel(const double* part, int G, int nq, KState* ks, int fkind, int emode, int col, double* hstat,
-                const int* skip, const int* skip2) {
+finalize_kernel(const double* part, int G, int /*nq: the grid for FK_H*/, KState* ks, int fkind, int emode,
+                int col, double* hstat, const int* skip, const int* skip2) {
   if (skipped(skip, skip2)) return;
   __shared__ double red[16];
   __shared__ double tot[1];

@@ -136,7 +136,7 @@ __host__ __device__ constexpr int cols_per_tile(int P) {
 
 template <typename T, int EPT, int R>
 __device__ __forceinline__ void fft_pass(cx<T>* buf, int LS, int logPr, int Ls, int logR,
-                                         const cx<T>* tw, int P, int twshift) {
+                                         const cx<T>* tw, int twshift) {
   constexpr int NB = EPT / R;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int Pr = 1 << logPr;
@@ -191,7 +191,7 @@ __device__ __forceinline__ void fft_lines_ct(cx<T>* buf, int LS, const cx<T>* tw
     constexpr int LOGE = ilog2c(EPT);   // a pass's radix is at most EPT
     constexpr int LOGR0 = REM >= 3 ? 3 : REM;
     constexpr int LOGR = LOGR0 < LOGE ? LOGR0 : LOGE;
-    fft_pass<T, EPT, (1 << LOGR)>(buf, LS, LOGP - LOGR, 1 << LOGLS, LOGR, tw, 1 << LOGP, LOGP + 1 - LOGLS - LOGR);
+    fft_pass<T, EPT, (1 << LOGR)>(buf, LS, LOGP - LOGR, 1 << LOGLS, LOGR, tw, LOGP + 1 - LOGLS - LOGR);
     fft_lines_ct<T, EPT, LOGP, LOGLS + LOGR>(buf, LS, tw);
   }
 }
@@ -200,19 +200,18 @@ __device__ __forceinline__ void fft_lines_ct(cx<T>* buf, int LS, const cx<T>* tw
 // synchronised after writing the input; results are visible on return.
 template <typename T, int EPT>
 __device__ __forceinline__ void fft_lines(cx<T>* buf, int LS, int logP, const cx<T>* tw) {
-  const int P = 1 << logP;
   int logLs = 0;
   while (logLs < logP) {
     const int rem = logP - logLs;
     const int Ls = 1 << logLs;
     if (rem >= 3) {
-      fft_pass<T, EPT, 8>(buf, LS, logP - 3, Ls, 3, tw, P, logP + 1 - logLs - 3);
+      fft_pass<T, EPT, 8>(buf, LS, logP - 3, Ls, 3, tw, logP + 1 - logLs - 3);
       logLs += 3;
     } else if (rem == 2) {
-      fft_pass<T, EPT, 4>(buf, LS, logP - 2, Ls, 2, tw, P, logP + 1 - logLs - 2);
+      fft_pass<T, EPT, 4>(buf, LS, logP - 2, Ls, 2, tw, logP + 1 - logLs - 2);
       logLs += 2;
     } else {
-      fft_pass<T, EPT, 2>(buf, LS, logP - 1, Ls, 1, tw, P, logP + 1 - logLs - 1);
+      fft_pass<T, EPT, 2>(buf, LS, logP - 1, Ls, 1, tw, logP + 1 - logLs - 1);
       logLs += 1;
     }
   }
