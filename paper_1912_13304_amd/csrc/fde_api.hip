@@ -25,6 +25,7 @@
 #include "fde_host.hpp"
 #include "fde_krylov.hpp"
 #include "fde_lines.hpp"
+#include "fde_pcg.hpp"
 #include "fde_tri.hpp"
 
 using namespace fde;
@@ -669,8 +670,9 @@ static void launch_line_k(const LineArgs<T>& a, int grid, int nth, size_t lds, h
 
 // COLS = true: d is a column direction (d.cols); only the y-direction
 // programs are instantiated in that form.
-template <typename T, int FL, bool COLS = false>
-static void launch_line(const Dir& d, LineArgs<T> a, hipStream_t st) {
+// The direction's sizes and strides into the line program's arguments.
+template <typename T>
+static void fill_line_args(const Dir& d, LineArgs<T>& a) {
   a.n = d.n;
   a.P = d.P;
   a.logP = d.logP;
@@ -681,6 +683,11 @@ static void launch_line(const Dir& d, LineArgs<T> a, hipStream_t st) {
   a.ls = d.ls;
   a.es = d.es;
   a.ntiles = (d.nlines + d.B - 1) / d.B;
+}
+
+template <typename T, int FL, bool COLS = false>
+static void launch_line(const Dir& d, LineArgs<T> a, hipStream_t st) {
+  fill_line_args(d, a);
   const int nth = std::max(1, d.B * d.P / 8);
   const size_t lds = ((size_t)d.B * a.LS + 2 * d.B + (size_t)d.P) * sizeof(cx<T>);
   const int grid = 8 * ((a.ntiles + 7) / 8);
@@ -1347,6 +1354,64 @@ static void dot_red(fde_plan pl, const T* a, const T* b, KState* ks, int emode, 
   finalize(pl, G, 1, ks, FK_DOT, emode, 0, nullptr, st, skip, nullptr);
 }
 
+// One (re)start of PCG in a single workgroup (fde_pcg.hpp): 1D plans whose
+// line fits one workgroup, with a line-program preconditioner.
+static bool pcg_one_workgroup(fde_plan pl) {
+  return pl->dim == 1 && !pl->big && pl->p.prec != FDE_P_NONE && pl->p.prec != FDE_P_TRI && pl->rows.logP >= 3 &&
+         pl->rows.logP <= 12;
+}
+
+template <int LOGP>
+static fde_status pcg1d_launch(fde_plan pl, const LineArgs<double>& ta, const LineArgs<double>& ma, double* x,
+                               double* r, double* p, double* q, double* z, hipStream_t st) {
+  const Dir& d = pl->rows;
+  const size_t lds = ((size_t)d.B * line_stride(d.P) + 2 * d.B + (size_t)d.P) * sizeof(cx<double>);
+  // the kernel also holds a few hundred bytes of static LDS, so the dynamic
+  // size asked for is the launch's own (one value per LOGP), not the CU's 160 KB
+  static bool attr_set = false;
+  if (!attr_set) {
+    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&pcg1d_kernel<LOGP>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((pcg1d_kernel<LOGP>), dim3(1), dim3(d.B * d.P / 8), lds, st, ta, ma, x, r, p, q, z,
+                     (int)pl->N, pl->ks, pl->hstat_dev);
+  HIPCHK(hipGetLastError());
+  return FDE_OK;
+}
+
+static fde_status pcg_restart_one_workgroup(fde_plan pl, double* x, double* r, double* p, double* q, double* z,
+                                            hipStream_t st) {
+  const Consts<double>& c = consts<double>(pl);
+  LineArgs<double> ta{};   // z = P^{-1} r, as tau_only
+  ta.in = r;
+  ta.pre = (pl->has_dinv && pl->dside == FDE_D_LEFT) ? c.dinv : nullptr;
+  ta.post = (pl->has_dinv && pl->dside == FDE_D_RIGHT) ? c.dinv : nullptr;
+  ta.fline = c.fzero;
+  ta.felem = c.fx;
+  ta.W2 = c.W2x;
+  ta.out = z;
+  fill_line_args(pl->rows, ta);
+  LineArgs<double> ma = toep_args<double>(pl, false, nullptr, nullptr);   // q = M p, as matvec_only
+  ma.in = p;
+  ma.bscale = pl->nu;
+  ma.tscale = 1.0;
+  ma.out = q;
+  fill_line_args(pl->rows, ma);
+  switch (pl->rows.logP) {
+    case 3: return pcg1d_launch<3>(pl, ta, ma, x, r, p, q, z, st);
+    case 4: return pcg1d_launch<4>(pl, ta, ma, x, r, p, q, z, st);
+    case 5: return pcg1d_launch<5>(pl, ta, ma, x, r, p, q, z, st);
+    case 6: return pcg1d_launch<6>(pl, ta, ma, x, r, p, q, z, st);
+    case 7: return pcg1d_launch<7>(pl, ta, ma, x, r, p, q, z, st);
+    case 8: return pcg1d_launch<8>(pl, ta, ma, x, r, p, q, z, st);
+    case 9: return pcg1d_launch<9>(pl, ta, ma, x, r, p, q, z, st);
+    case 10: return pcg1d_launch<10>(pl, ta, ma, x, r, p, q, z, st);
+    case 11: return pcg1d_launch<11>(pl, ta, ma, x, r, p, q, z, st);
+    default: return pcg1d_launch<12>(pl, ta, ma, x, r, p, q, z, st);   // pcg_one_workgroup: logP <= 12
+  }
+}
+
 static fde_status solve_pcg(fde_plan pl, const double* b, double* x, fde_info* info, hipStream_t st) {
   const long N = pl->N;
   KState* ks = pl->ks;
@@ -1372,6 +1437,15 @@ static fde_status solve_pcg(fde_plan pl, const double* b, double* x, fde_info* i
   const int G = red_grid(N, (long)RED_THREADS * 8);
   int restarts = 0;
   while (!pl->hks->conv && !pl->hks->nonfinite && pl->hks->iters < pl->p.maxit) {
+    if (pcg_one_workgroup(pl)) {
+      TRY(pcg_restart_one_workgroup(pl, x, r, p, q, z, st));
+      matvec_only<double>(pl, x, q, pl->nu, 1.0, st, nullptr);   // true residual
+      norm_red<double>(pl, b, q, r, ks, EP_RESID, st);
+      HIPCHK(hipGetLastError());
+      TRY(read_header(pl, ks, st));
+      if (!pl->hks->conv) ++restarts;
+      continue;
+    }
     // (re)start: z = P^{-1} r, rz = r.z, p = z
     tau_only<double>(pl, r, nullptr, z, st, skip);
     dot_red<double>(pl, r, z, ks, EP_CG_RZ, st, skip);

@@ -266,12 +266,12 @@ __device__ __forceinline__ int xcd_tile(int ntiles) {
 // (line stride 1, element stride n1), and consecutive threads take the B
 // entries of one row, so that the global accesses of a wavefront are row
 // segments rather than single elements.
+// The program on tile `tile` (B lines): the body of line_kernel, also run
+// by the single-workgroup PCG kernel.  Every thread of the workgroup calls
+// it; it reads its operands from global memory and writes its results there.
 template <typename T, bool COLS, int FL, int LOGP>
-__global__ void __launch_bounds__(512) line_kernel(LineArgs<T> a) {
+__device__ __forceinline__ void line_body(const LineArgs<T>& a, int tile) {
   constexpr int EPT = 8;
-  if ((a.skip && *a.skip) || (a.skip2 && *a.skip2)) return;
-  const int tile = xcd_tile(a.ntiles);
-  if (tile >= a.ntiles) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
 
@@ -534,6 +534,14 @@ __global__ void __launch_bounds__(512) line_kernel(LineArgs<T> a) {
       a.out[gi[i]] = a.bscale * b + a.tscale * acc[i];
     }
   }
+}
+
+template <typename T, bool COLS, int FL, int LOGP>
+__global__ void __launch_bounds__(512) line_kernel(LineArgs<T> a) {
+  if ((a.skip && *a.skip) || (a.skip2 && *a.skip2)) return;
+  const int tile = xcd_tile(a.ntiles);
+  if (tile >= a.ntiles) return;
+  line_body<T, COLS, FL, LOGP>(a, tile);
 }
 
 }  // namespace fde

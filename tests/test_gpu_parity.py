@@ -227,6 +227,66 @@ def test_pcg_constant_1d_full_size():
     assert relerr(xg, xo) < 1e-10
 
 
+def const_problem(n, alpha, d):
+    p = fi.constant_1d(n=n, alpha=alpha, seed=n)
+    p.dplus = np.full(n, d)
+    p.dminus = np.full(n, d)
+    return p
+
+
+@pytest.mark.parametrize("n,alpha", [(7, 1.5), (15, 1.9), (63, 1.2), (511, 1.7), (2047, 1.5), (4095, 1.3),
+                                     (8191, 1.5)])
+@pytest.mark.parametrize("d", [1.0, 1.3])
+def test_pcg_constant_1d_sizes(n, alpha, d):
+    """PCG + P_F on constant coefficients from a nonzero start, to 1e-10.
+    n + 1 <= 4096 runs each (re)start of the iteration in one workgroup,
+    n = 8191 the multi-kernel loop; both take the oracle's PCG steps."""
+    fde = need_gpu()
+    p = const_problem(n, alpha, d)
+    x0 = np.random.default_rng(n).uniform(-1, 1, n)
+    xo, io = oracle_solve(p, p.b, x0, tol=1e-10, solver="pcg")
+    xg, ig = gpu_solve(fde, p, p.b, x0)
+    assert ig.converged and io["converged"]
+    assert abs(ig.iters - io["iters"]) <= 1, (ig.iters, io["iters"])
+    assert relerr(xg, xo) < 1e-10
+    s = FDESystem.from_problem(p)
+    assert relerr(s.matvec(xg), p.b) <= 1e-10 * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("kind", ["tau_hat", "tilde"])
+def test_pcg_other_preconditioners(kind):
+    fde = need_gpu()
+    p = const_problem(1023, 1.6, 1.3)
+    s = FDESystem.from_problem(p)
+    xo, io = krylov.pcg(s.matvec, p.b, pc.make(kind, s), tol=1e-10)
+    prec = fde.P_TAU_HAT if kind == "tau_hat" else fde.P_TILDE
+    xg, ig = gpu_solve(fde, p, p.b, np.zeros(p.N), prec=prec)
+    assert ig.converged and io["converged"]
+    assert abs(ig.iters - io["iters"]) <= 1, (ig.iters, io["iters"])
+    assert relerr(xg, xo) < 1e-10
+
+
+@pytest.mark.parametrize("n", [255, 8191])
+def test_pcg_maxit_and_repeat(n):
+    """The iteration cap stops PCG with FDE_ENOTCONV and the oracle's iterate
+    after that many steps; a second solve on the same plan repeats the first
+    bit for bit."""
+    fde = need_gpu()
+    p = const_problem(n, 1.5, 1.0)
+    s = FDESystem.from_problem(p)
+    xo, io = krylov.pcg(s.matvec, p.b, pc.make("tau", s), tol=1e-10, maxit=3)
+    with fde.Plan(p, maxit=3) as plan:
+        runs = []
+        for _ in range(2):
+            x = dev(np.zeros(n))
+            info = plan.solve(dev(p.b), x, allow_notconv=True)
+            runs.append((host(x), info.iters, info.converged))
+    for xg, iters, conv in runs:
+        assert iters == 3 and not conv
+        assert relerr(xg, xo) < 1e-10
+    assert np.array_equal(runs[0][0], runs[1][0])
+
+
 def test_zero_rhs_and_nonfinite():
     fde = need_gpu()
     p = fi.variable_1d(n=63)
