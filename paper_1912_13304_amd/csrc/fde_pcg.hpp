@@ -21,9 +21,11 @@
 namespace fde {
 
 // ta: z = P^{-1} r (in = r, out = z); ma: q = nu p + T-part (in = p, out = q).
-// Launched with one workgroup of the line program's size.
+// Launched with one workgroup of the line program's size, P/8 threads (64
+// below P = 512); the bound is that size so that the registers of the three
+// inlined line programs fit without spilling.
 template <int LOGP>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__((1 << LOGP) / 8 > 64 ? (1 << LOGP) / 8 : 64)
 pcg1d_kernel(LineArgs<double> ta, LineArgs<double> ma, double* x, double* r, double* p, double* q, double* z,
              int n, KState* ks, double* hstat) {
   __shared__ double red[16];
@@ -34,6 +36,15 @@ pcg1d_kernel(LineArgs<double> ta, LineArgs<double> ma, double* x, double* r, dou
   const int maxit = ks->maxit;
   int iters = ks->iters;
   const double rz_prev = ks->rz;
+  // Each inlined line program's address arithmetic depends on its tile; a
+  // tile index the compiler cannot see through keeps it from hoisting three
+  // copies of that arithmetic out of the loop, which would not fit in
+  // registers.  The value is always 0.
+  auto tile0 = []() {
+    int t = 0;
+    asm volatile("" : "+s"(t));
+    return t;
+  };
   auto dot = [&](const double* u, const double* v) -> double {
     double acc[1] = {0.0};
     for (int e = tid; e < n; e += nt) acc[0] += u[e] * v[e];
@@ -42,7 +53,7 @@ pcg1d_kernel(LineArgs<double> ta, LineArgs<double> ma, double* x, double* r, dou
     __syncthreads();   // red and tot are reused by the next sum
     return s;
   };
-  line_body<double, false, LF_DST1 | LF_FDST2, LOGP>(ta, 0);   // z = P^{-1} r
+  line_body<double, false, LF_DST1 | LF_FDST2, LOGP>(ta, tile0());   // z = P^{-1} r
   __syncthreads();
   double rz = dot(r, z);
   if (tid == 0) {
@@ -52,7 +63,7 @@ pcg1d_kernel(LineArgs<double> ta, LineArgs<double> ma, double* x, double* r, dou
   for (int e = tid; e < n; e += nt) p[e] = z[e];
   __syncthreads();
   for (;;) {
-    line_body<double, false, LF_TOEP, LOGP>(ma, 0);   // q = M p
+    line_body<double, false, LF_TOEP, LOGP>(ma, tile0());   // q = M p
     __syncthreads();
     const double pq = dot(p, q);
     const double alpha = rz / pq;
@@ -84,7 +95,7 @@ pcg1d_kernel(LineArgs<double> ta, LineArgs<double> ma, double* x, double* r, dou
       }
     }
     if (done) break;   // uniform: every thread holds the same est and iters
-    line_body<double, false, LF_DST1 | LF_FDST2, LOGP>(ta, 0);   // z = P^{-1} r
+    line_body<double, false, LF_DST1 | LF_FDST2, LOGP>(ta, tile0());   // z = P^{-1} r
     __syncthreads();
     const double rzn = dot(r, z);
     const double beta = rz != 0.0 ? rzn / rz : 0.0;
