@@ -278,6 +278,24 @@ def table_paper2d(fi, fde, torch, np):
     return rows
 
 
+def pcg_leg(fi, fde, torch, np, solves=20):
+    """The 1D constant-coefficient system (d+ = d- = 1, n = 1023, alpha =
+    1.5) solved by PCG with the Case I preconditioner to 1e-10 from x0 = 0:
+    time-to-tol per solve, host clock around each solve."""
+    p = fi.constant_1d()
+    with fde.Plan(p) as plan:
+        b = torch.as_tensor(p.b, dtype=torch.float64, device="cuda").contiguous()
+        times, info = [], None
+        for _ in range(solves):
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = plan.solve(b, x)
+            times.append(time.perf_counter() - t0)
+    return {"time_to_tol_us_min": 1e6 * min(times), "time_to_tol_us_median": 1e6 * float(np.median(times)),
+            "iters": info.iters, "relres": info.relres_true, "converged": bool(info.converged)}
+
+
 def one_d_legs(args, fi, fde, torch, np):
     """The 1D workloads: (a) the constant-coefficient system (d+ = d- = 1,
     n = 1023, alpha = 1.5) solved by PCG with the Case I preconditioner to
@@ -287,19 +305,7 @@ def one_d_legs(args, fi, fde, torch, np):
     float64 FGMRES, no inner Krylov: inner_steps = 0, the faster mixed form on
     long 1D lines), solves per second."""
     T = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda").reshape(-1).contiguous()
-    out = {}
-    p = fi.constant_1d()
-    with fde.Plan(p) as plan:
-        b = T(p.b)
-        times, info = [], None
-        for _ in range(20):
-            x = torch.zeros_like(b)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            info = plan.solve(b, x)
-            times.append(time.perf_counter() - t0)
-    out["pcg_constant_1023"] = {"time_to_tol_us_min": 1e6 * min(times), "time_to_tol_us_median": 1e6 * float(np.median(times)),
-                                "iters": info.iters, "relres": info.relres_true, "converged": bool(info.converged)}
+    out = {"pcg_constant_1023": pcg_leg(fi, fde, torch, np)}
     log(f"[bench] 1D PCG: {out['pcg_constant_1023']}")
     jobs = {}
     for alpha in (1.2, 1.5, 1.8):
@@ -350,6 +356,8 @@ def main():
                     help="instances solved one plan at a time for the batched-vs-plan comparison")
     ap.add_argument("--only-batched", action="store_true",
                     help="run the batched leg alone (profiling); prints its JSON object")
+    ap.add_argument("--only-pcg", action="store_true",
+                    help="run the 1D constant-coefficient PCG leg alone (profiling); prints its JSON object")
     ap.add_argument("--table", choices=["variants", "paper2d"], default=None,
                     help="print a table instead of the benchmark line: preconditioner variants at the "
                          "workload sizes, or the paper's 2D examples extended to n = 1023")
@@ -370,6 +378,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.only_batched:
         print(json.dumps({"batched": batched_leg(args, fi, fde, torch, np)}), flush=True)
+        return
+    if args.only_pcg:
+        print(json.dumps({"pcg_constant_1023": pcg_leg(fi, fde, torch, np, solves=50)}), flush=True)
         return
     if args.table == "variants":
         print(json.dumps({"table": "variants", "rows": table_variants(fi, fde, torch, np)}), flush=True)
