@@ -1354,16 +1354,21 @@ static void dot_red(fde_plan pl, const T* a, const T* b, KState* ks, int emode, 
   finalize(pl, G, 1, ks, FK_DOT, emode, 0, nullptr, st, skip, nullptr);
 }
 
-// One (re)start of PCG in a single workgroup (fde_pcg.hpp): 1D plans whose
+// The whole PCG solve in a single workgroup (fde_pcg.hpp): 1D plans whose
 // line fits one workgroup, with a line-program preconditioner.
 static bool pcg_one_workgroup(fde_plan pl) {
   return pl->dim == 1 && !pl->big && pl->p.prec != FDE_P_NONE && pl->p.prec != FDE_P_TRI && pl->rows.logP >= 3 &&
          pl->rows.logP <= 12;
 }
 
+struct PcgArgs {
+  LineArgs<double> ta, ma, xa;
+  const double* b;
+  double *x, *r, *p, *q, *z;
+};
+
 template <int LOGP>
-static fde_status pcg1d_launch(fde_plan pl, const LineArgs<double>& ta, const LineArgs<double>& ma, double* x,
-                               double* r, double* p, double* q, double* z, hipStream_t st) {
+static fde_status pcg1d_launch(fde_plan pl, const PcgArgs& g, hipStream_t st) {
   const Dir& d = pl->rows;
   const size_t lds = ((size_t)d.B * line_stride(d.P) + 2 * d.B + (size_t)d.P) * sizeof(cx<double>);
   // the kernel also holds a few hundred bytes of static LDS, so the dynamic
@@ -1374,45 +1379,72 @@ static fde_status pcg1d_launch(fde_plan pl, const LineArgs<double>& ta, const Li
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr_set = true;
   }
-  hipLaunchKernelGGL((pcg1d_kernel<LOGP>), dim3(1), dim3(d.B * d.P / 8), lds, st, ta, ma, x, r, p, q, z,
-                     (int)pl->N, pl->ks, pl->hstat_dev);
+  hipLaunchKernelGGL((pcg1d_kernel<LOGP>), dim3(1), dim3(d.B * d.P / 8), lds, st, g.ta, g.ma, g.xa, g.b, g.x, g.r,
+                     g.p, g.q, g.z, (int)pl->N, pl->p.tol, pl->p.maxit, pl->ks);
   HIPCHK(hipGetLastError());
   return FDE_OK;
 }
 
-static fde_status pcg_restart_one_workgroup(fde_plan pl, double* x, double* r, double* p, double* q, double* z,
-                                            hipStream_t st) {
+static fde_status solve_pcg_one_workgroup(fde_plan pl, const double* b, double* x, fde_info* info,
+                                          hipStream_t st) {
   const Consts<double>& c = consts<double>(pl);
-  LineArgs<double> ta{};   // z = P^{-1} r, as tau_only
-  ta.in = r;
-  ta.pre = (pl->has_dinv && pl->dside == FDE_D_LEFT) ? c.dinv : nullptr;
-  ta.post = (pl->has_dinv && pl->dside == FDE_D_RIGHT) ? c.dinv : nullptr;
-  ta.fline = c.fzero;
-  ta.felem = c.fx;
-  ta.W2 = c.W2x;
-  ta.out = z;
-  fill_line_args(pl->rows, ta);
-  LineArgs<double> ma = toep_args<double>(pl, false, nullptr, nullptr);   // q = M p, as matvec_only
-  ma.in = p;
-  ma.bscale = pl->nu;
-  ma.tscale = 1.0;
-  ma.out = q;
-  fill_line_args(pl->rows, ma);
+  PcgArgs g{};
+  g.b = b;
+  g.x = x;
+  g.r = pl->V;
+  g.p = pl->V + pl->ld;
+  g.q = pl->V + 2 * pl->ld;
+  g.z = pl->Z;
+  g.ta.in = g.r;   // z = P^{-1} r, as tau_only
+  g.ta.pre = (pl->has_dinv && pl->dside == FDE_D_LEFT) ? c.dinv : nullptr;
+  g.ta.post = (pl->has_dinv && pl->dside == FDE_D_RIGHT) ? c.dinv : nullptr;
+  g.ta.fline = c.fzero;
+  g.ta.felem = c.fx;
+  g.ta.W2 = c.W2x;
+  g.ta.out = g.z;
+  fill_line_args(pl->rows, g.ta);
+  g.ma = toep_args<double>(pl, false, nullptr, nullptr);   // q = M p, as matvec_only
+  g.ma.in = g.p;
+  g.ma.bscale = pl->nu;
+  g.ma.tscale = 1.0;
+  g.ma.out = g.q;
+  fill_line_args(pl->rows, g.ma);
+  g.xa = g.ma;   // q = M x
+  g.xa.in = x;
   switch (pl->rows.logP) {
-    case 3: return pcg1d_launch<3>(pl, ta, ma, x, r, p, q, z, st);
-    case 4: return pcg1d_launch<4>(pl, ta, ma, x, r, p, q, z, st);
-    case 5: return pcg1d_launch<5>(pl, ta, ma, x, r, p, q, z, st);
-    case 6: return pcg1d_launch<6>(pl, ta, ma, x, r, p, q, z, st);
-    case 7: return pcg1d_launch<7>(pl, ta, ma, x, r, p, q, z, st);
-    case 8: return pcg1d_launch<8>(pl, ta, ma, x, r, p, q, z, st);
-    case 9: return pcg1d_launch<9>(pl, ta, ma, x, r, p, q, z, st);
-    case 10: return pcg1d_launch<10>(pl, ta, ma, x, r, p, q, z, st);
-    case 11: return pcg1d_launch<11>(pl, ta, ma, x, r, p, q, z, st);
-    default: return pcg1d_launch<12>(pl, ta, ma, x, r, p, q, z, st);   // pcg_one_workgroup: logP <= 12
+    case 3: TRY(pcg1d_launch<3>(pl, g, st)); break;
+    case 4: TRY(pcg1d_launch<4>(pl, g, st)); break;
+    case 5: TRY(pcg1d_launch<5>(pl, g, st)); break;
+    case 6: TRY(pcg1d_launch<6>(pl, g, st)); break;
+    case 7: TRY(pcg1d_launch<7>(pl, g, st)); break;
+    case 8: TRY(pcg1d_launch<8>(pl, g, st)); break;
+    case 9: TRY(pcg1d_launch<9>(pl, g, st)); break;
+    case 10: TRY(pcg1d_launch<10>(pl, g, st)); break;
+    case 11: TRY(pcg1d_launch<11>(pl, g, st)); break;
+    default: TRY(pcg1d_launch<12>(pl, g, st)); break;   // pcg_one_workgroup: logP <= 12
   }
+  TRY(read_header(pl, pl->ks, st));
+  const KState h = *pl->hks;
+  if (!std::isfinite(h.bnorm)) return fail(FDE_ENONFINITE, "the right-hand side has a non-finite value");
+  if (h.bnorm == 0.0) {
+    if (info) *info = fde_info{0, 0, 0, 1, 0.0, 0.0, 0.0};
+    return FDE_OK;
+  }
+  if (info) {
+    info->iters = h.iters;
+    info->inner_iters = 0;
+    info->restarts = h.restarts;
+    info->converged = h.conv;
+    info->relres_true = h.beta / h.bnorm;
+    info->relres_est = h.est / h.bnorm;
+  }
+  if (h.nonfinite) return fail(FDE_ENONFINITE, "a residual became non-finite");
+  if (!h.conv) return fail(FDE_ENOTCONV, "tolerance not reached in %d iterations", h.iters);
+  return FDE_OK;
 }
 
 static fde_status solve_pcg(fde_plan pl, const double* b, double* x, fde_info* info, hipStream_t st) {
+  if (pcg_one_workgroup(pl)) return solve_pcg_one_workgroup(pl, b, x, info, st);
   const long N = pl->N;
   KState* ks = pl->ks;
   const int* skip = &ks->done;
@@ -1437,15 +1469,6 @@ static fde_status solve_pcg(fde_plan pl, const double* b, double* x, fde_info* i
   const int G = red_grid(N, (long)RED_THREADS * 8);
   int restarts = 0;
   while (!pl->hks->conv && !pl->hks->nonfinite && pl->hks->iters < pl->p.maxit) {
-    if (pcg_one_workgroup(pl)) {
-      TRY(pcg_restart_one_workgroup(pl, x, r, p, q, z, st));
-      matvec_only<double>(pl, x, q, pl->nu, 1.0, st, nullptr);   // true residual
-      norm_red<double>(pl, b, q, r, ks, EP_RESID, st);
-      HIPCHK(hipGetLastError());
-      TRY(read_header(pl, ks, st));
-      if (!pl->hks->conv) ++restarts;
-      continue;
-    }
     // (re)start: z = P^{-1} r, rz = r.z, p = z
     tau_only<double>(pl, r, nullptr, z, st, skip);
     dot_red<double>(pl, r, z, ks, EP_CG_RZ, st, skip);

@@ -38,7 +38,8 @@ struct KState {
   int breakdown;
   double bnorm, tolabs, beta, est, hn;
   double rz, pq, alpha, betacg;
-  int pad0_, pad1_;
+  int restarts;     // PCG restarts, set by the one-workgroup solve
+  int pad1_;
   // ---- body ----
   double scale[KMAX + 1];   // basis vector i = scale[i] * stored vector i
   double h1[KMAX + 1], h2[KMAX + 1];
