@@ -239,7 +239,7 @@ def const_problem(n, alpha, d):
 @pytest.mark.parametrize("d", [1.0, 1.3])
 def test_pcg_constant_1d_sizes(n, alpha, d):
     """PCG + P_F on constant coefficients from a nonzero start, to 1e-10.
-    n + 1 <= 4096 runs each (re)start of the iteration in one workgroup,
+    n + 1 <= 4096 runs the whole solve in one workgroup,
     n = 8191 the multi-kernel loop; both take the oracle's PCG steps."""
     fde = need_gpu()
     p = const_problem(n, alpha, d)
@@ -285,6 +285,32 @@ def test_pcg_maxit_and_repeat(n):
         assert iters == 3 and not conv
         assert relerr(xg, xo) < 1e-10
     assert np.array_equal(runs[0][0], runs[1][0])
+
+
+@pytest.mark.parametrize("n", [63, 8191])
+def test_pcg_zero_rhs_and_nonfinite(n):
+    """PCG (one workgroup at n = 63, multi-kernel at n = 8191): b = 0 gives
+    x = 0 in no iterations; a NaN in b or an Inf in x0 is FDE_ENONFINITE."""
+    fde = need_gpu()
+    p = const_problem(n, 1.5, 1.0)
+    with fde.Plan(p) as plan:
+        x = dev(np.ones(n))
+        info = plan.solve(dev(np.zeros(n)), x)
+        assert info.iters == 0 and info.converged
+        assert np.all(host(x) == 0)
+        b = p.b.copy()
+        b[5] = np.nan
+        with pytest.raises(fde.FdeError) as e:
+            plan.solve(dev(b), dev(np.zeros(n)))
+        assert e.value.status == fde.FDE_ENONFINITE
+        x0 = np.zeros(n)
+        x0[3] = np.inf
+        with pytest.raises(fde.FdeError) as e:
+            plan.solve(dev(p.b), dev(x0))
+        assert e.value.status == fde.FDE_ENONFINITE
+        x = dev(np.zeros(n))   # the plan still solves after the errors
+        info = plan.solve(dev(p.b), x)
+        assert info.converged
 
 
 def test_zero_rhs_and_nonfinite():
