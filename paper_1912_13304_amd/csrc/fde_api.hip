@@ -1379,7 +1379,7 @@ static fde_status pcg1d_launch(fde_plan pl, const PcgArgs& g, hipStream_t st) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr_set = true;
   }
-  hipLaunchKernelGGL((pcg1d_kernel<LOGP>), dim3(1), dim3(d.B * d.P / 8), lds, st, g.ta, g.ma, g.xa, g.b, g.x, g.r,
+  hipLaunchKernelGGL((pcg1d_kernel<LOGP>), dim3(1), dim3(pcg_threads(LOGP)), lds, st, g.ta, g.ma, g.xa, g.b, g.x, g.r,
                      g.p, g.q, g.z, (int)pl->N, pl->p.tol, pl->p.maxit, pl->ks);
   HIPCHK(hipGetLastError());
   return FDE_OK;

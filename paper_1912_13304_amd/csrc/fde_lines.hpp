@@ -269,9 +269,9 @@ __device__ __forceinline__ int xcd_tile(int ntiles) {
 // The program on tile `tile` (B lines): the body of line_kernel, also run
 // by the single-workgroup PCG kernel.  Every thread of the workgroup calls
 // it; it reads its operands from global memory and writes its results there.
-template <typename T, bool COLS, int FL, int LOGP>
+// EPT: elements per thread (8; 4 takes twice the threads, radix-4 passes).
+template <typename T, bool COLS, int FL, int LOGP, int EPT = 8>
 __device__ __forceinline__ void line_body(const LineArgs<T>& a, int tile) {
-  constexpr int EPT = 8;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
 

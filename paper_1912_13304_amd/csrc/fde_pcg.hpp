@@ -24,12 +24,20 @@
 
 namespace fde {
 
+// Elements per thread of the line programs: 4 up to P = 2048 (P/4 threads,
+// at least 128: every SIMD of the CU takes a wave), 8 at P = 4096 (512
+// threads).
+__host__ __device__ constexpr int pcg_ept(int logP) { return logP <= 11 ? 4 : 8; }
+__host__ __device__ constexpr int pcg_threads(int logP) {
+  return rows_per_tile(1 << logP) * (1 << logP) / pcg_ept(logP);
+}
+
 // ta: z = P^{-1} r (in = r, out = z); ma: q = nu p + T-part (in = p, out = q);
 // xa: the same product of x (in = x, out = q).  Launched with one workgroup
-// of the line program's size, P/8 threads (64 below P = 512); the bound is
-// that size so that the registers of the three inlined line programs fit.
+// of pcg_threads(LOGP) threads; the bound is that size so that the registers
+// of the three inlined line programs fit.
 template <int LOGP>
-__global__ void __launch_bounds__((1 << LOGP) / 8 > 64 ? (1 << LOGP) / 8 : 64)
+__global__ void __launch_bounds__(pcg_threads(LOGP))
 pcg1d_kernel(LineArgs<double> ta, LineArgs<double> ma, LineArgs<double> xa, const double* b, double* x,
              double* r, double* p, double* q, double* z, int n, double tol, int maxit, KState* ks) {
   __shared__ double red[16];
@@ -66,7 +74,7 @@ pcg1d_kernel(LineArgs<double> ta, LineArgs<double> ma, LineArgs<double> xa, cons
     conv = 1;
   } else if (!nonfinite) {
     for (bool started = false;; started = true) {
-      line_body<double, false, LF_TOEP, LOGP>(xa, tile0());   // q = M x
+      line_body<double, false, LF_TOEP, LOGP, pcg_ept(LOGP)>(xa, tile0());   // q = M x
       __syncthreads();
       double ss = 0.0;
       for (int e = tid; e < n; e += nt) {
@@ -81,7 +89,7 @@ pcg1d_kernel(LineArgs<double> ta, LineArgs<double> ma, LineArgs<double> xa, cons
       if (conv || nonfinite || iters >= maxit) break;
       // one (re)start of PCG from r
       for (bool first = true;; first = false) {
-        line_body<double, false, LF_DST1 | LF_FDST2, LOGP>(ta, tile0());   // z = P^{-1} r
+        line_body<double, false, LF_DST1 | LF_FDST2, LOGP, pcg_ept(LOGP)>(ta, tile0());   // z = P^{-1} r
         __syncthreads();
         const double rzn = dot(r, z);
         if (first) {
@@ -93,7 +101,7 @@ pcg1d_kernel(LineArgs<double> ta, LineArgs<double> ma, LineArgs<double> xa, cons
         }
         rz = rzn;
         __syncthreads();
-        line_body<double, false, LF_TOEP, LOGP>(ma, tile0());   // q = M p
+        line_body<double, false, LF_TOEP, LOGP, pcg_ept(LOGP)>(ma, tile0());   // q = M p
         __syncthreads();
         pq = dot(p, q);
         alpha = rz / pq;
