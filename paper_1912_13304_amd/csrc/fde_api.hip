@@ -659,12 +659,10 @@ struct ProbePlanScope {
 
 template <typename T, bool COLS, int FL, int LOGP>
 static void launch_line_k(const LineArgs<T>& a, int grid, int nth, size_t lds, hipStream_t st) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&line_kernel<T, COLS, FL, LOGP>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attr_set = true;
-  }
+  // function-local static: initialised once, thread-safe (server workers launch concurrently)
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&line_kernel<T, COLS, FL, LOGP>),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  (void)attr;
   hipLaunchKernelGGL((line_kernel<T, COLS, FL, LOGP>), dim3(grid), dim3(nth), lds, st, a);
 }
 
@@ -802,12 +800,10 @@ static void fourstep_k(LD in, cx<T>* out, long P, int npl, int batch, long ils, 
   constexpr int L = 1 << LOG;
   constexpr int B = fourstep_lines(L);
   constexpr int EPT = fourstep_ept(L);
-  static bool attr_set = false;
-  if (!attr_set) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&fourstep_kernel<T, LOG, CIN, COUT, LD>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attr_set = true;
-  }
+  static const hipError_t attr = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&fourstep_kernel<T, LOG, CIN, COUT, LD>), hipFuncAttributeMaxDynamicSharedMemorySize,
+      160 * 1024);
+  (void)attr;
   const size_t lds = ((size_t)B * line_stride(L) + (size_t)B * L) * sizeof(cx<T>);
   const long lines = (long)batch * npl;   // B divides npl (both powers of two, npl >= 64 >= B)
   hipLaunchKernelGGL((fourstep_kernel<T, LOG, CIN, COUT, LD>), dim3((unsigned)(lines / B)), dim3(B * L / EPT), lds, st, in,
@@ -1373,12 +1369,9 @@ static fde_status pcg1d_launch(fde_plan pl, const PcgArgs& g, hipStream_t st) {
   const size_t lds = ((size_t)d.B * line_stride(d.P) + 2 * d.B + (size_t)d.P) * sizeof(cx<double>);
   // the kernel also holds a few hundred bytes of static LDS, so the dynamic
   // size asked for is the launch's own (one value per LOGP), not the CU's 160 KB
-  static bool attr_set = false;
-  if (!attr_set) {
-    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&pcg1d_kernel<LOGP>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    attr_set = true;
-  }
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&pcg1d_kernel<LOGP>),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  HIPCHK(attr);
   hipLaunchKernelGGL((pcg1d_kernel<LOGP>), dim3(1), dim3(pcg_threads(LOGP)), lds, st, g.ta, g.ma, g.xa, g.b, g.x, g.r,
                      g.p, g.q, g.z, (int)pl->N, pl->p.tol, pl->p.maxit, pl->ks);
   HIPCHK(hipGetLastError());

@@ -95,7 +95,7 @@ Layout layout(const fde_params& p) {
     t[6] = take(g.blue ? g.Qs * 2 * r : 0);
   }
   const bool tri = p.prec == FDE_P_TRI;
-  L.tp = tri ? (int)std::max(1L, std::min((long)MMAX * 16, g.n / 2)) : 0;
+  L.tp = tri ? (int)std::max(1L, std::min((long)TRI_CHUNKS, g.n / 2)) : 0;
   for (int k = 0; k < 2; ++k) {
     const size_t r = k == 0 ? 8 : 4;
     size_t* t = k == 0 ? L.tri64 : L.tri32;
@@ -232,13 +232,11 @@ void destroy_impl(fde_batch bt) {
 
 template <int NT, int RAD>
 fde_status launch_v(const Args& a, int grid, hipStream_t st) {
-  static bool attr = false;
   const size_t lds = sizeof(Shm<NT>);
-  if (!attr) {
-    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_kernel<NT, RAD>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    attr = true;
-  }
+  // function-local static: initialised once, thread-safe
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_kernel<NT, RAD>),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  HIPCHK(attr);
   hipLaunchKernelGGL((batch_kernel<NT, RAD>), dim3(grid), dim3(NT), lds, st, a);
   HIPCHK(hipGetLastError());
   return FDE_OK;

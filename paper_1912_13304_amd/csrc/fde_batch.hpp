@@ -430,23 +430,29 @@ __device__ __forceinline__ double toep_any(const Inst& I, Shm<NT>& sh, const cx<
   return toep_op<T, NT, RAD, false>(I, sh, tw, logTW, x, base, c0, c1, c2, out, want_norm);
 }
 
-// z = P_tri^{-1}(s v) (Table 2) by the partitioned elimination: thread k
-// sweeps the interior of chunk k with the precomputed pivots, parallel cyclic
-// reduction over the chunk interfaces runs in LDS, and every row is then
-// recovered from its interior solution and the two neighbouring interfaces.
+// z = P_tri^{-1}(s v) (Table 2) by the partitioned elimination: chunk k's
+// interior is swept with the precomputed pivots (chunks are taken k = tid,
+// tid + NT, ..., so any chunk count up to TRI_CHUNKS works with any
+// workgroup size), parallel cyclic reduction over the chunk interfaces runs
+// in LDS, and every row is then recovered from its interior solution and the
+// two neighbouring interfaces.
+constexpr int TRI_CHUNKS = MMAX * 16;   // chunk count limit (assembly takes min(TRI_CHUNKS, n/2))
+
 template <typename T, int NT, typename Tin, typename Tout>
 __device__ __forceinline__ void tri_wg(const Inst& I, Shm<NT>& sh, const Tin* v, double s, Tout* z) {
+  constexpr int KP = (TRI_CHUNKS + NT - 1) / NT;   // chunks per thread
+  static_assert(4 * TRI_CHUNKS * sizeof(double) <= FFT_BYTES, "P_tri interface arrays exceed the LDS area");
   const Tab<T>& tb = tab<T>(I);
   const int tid = threadIdx.x, p = I.tp, n = I.n;
   const int* cs = I.tcs;
   T* y = tb.ty;
   T* sA = reinterpret_cast<T*>(sh.fft);
-  T* sB = sA + NT;
-  T* sC = sB + NT;
-  T* sD = sC + NT;
+  T* sB = sA + TRI_CHUNKS;
+  T* sC = sB + TRI_CHUNKS;
+  T* sD = sC + TRI_CHUNKS;
   const T scale = (T)s;
-  if (tid < p) {
-    const int s0 = cs[tid], r = cs[tid + 1] - 1;
+  for (int k = tid; k < p; k += NT) {
+    const int s0 = cs[k], r = cs[k + 1] - 1;
     T d = T(0);
     for (int i = s0; i < r; ++i) {
       d = ((T)v[i] * scale - tb.ai[i] * d) * tb.den[i];
@@ -457,48 +463,57 @@ __device__ __forceinline__ void tri_wg(const Inst& I, Shm<NT>& sh, const Tin* v,
       yn = y[i] - tb.cp[i] * yn;
       y[i] = yn;
     }
-    sD[tid] = (T)v[r] * scale - tb.ar[tid] * (r > s0 ? y[r - 1] : T(0));
+    sD[k] = (T)v[r] * scale - tb.ar[k] * (r > s0 ? y[r - 1] : T(0));
   }
   __syncthreads();
-  if (tid < p) {
-    if (tid + 1 < p) {
-      const int s2 = cs[tid + 1], q2 = cs[tid + 2] - 1 - s2;
-      if (q2 >= 1) sD[tid] -= tb.cr[tid] * y[s2];
+  for (int k = tid; k < p; k += NT) {
+    if (k + 1 < p) {
+      const int s2 = cs[k + 1], q2 = cs[k + 2] - 1 - s2;
+      if (q2 >= 1) sD[k] -= tb.cr[k] * y[s2];
     }
-    sA[tid] = tb.ra[tid];
-    sB[tid] = tb.rb[tid];
-    sC[tid] = tb.rc[tid];
+    sA[k] = tb.ra[k];
+    sB[k] = tb.rb[k];
+    sC[k] = tb.rc[k];
   }
   __syncthreads();
   for (int st = 1; st < p; st <<= 1) {
-    T nA = T(0), nB = T(0), nC = T(0), nD = T(0);
-    if (tid < p) {
-      const int km = tid - st, kp = tid + st;
-      nB = sB[tid];
-      nD = sD[tid];
-      if (km >= 0) {
-        const T al = -sA[tid] / sB[km];
-        nA = al * sA[km];
-        nB += al * sC[km];
-        nD += al * sD[km];
-      }
-      if (kp < p) {
-        const T ga = -sC[tid] / sB[kp];
-        nC = ga * sC[kp];
-        nB += ga * sA[kp];
-        nD += ga * sD[kp];
+    T nA[KP], nB[KP], nC[KP], nD[KP];
+#pragma unroll
+    for (int q = 0; q < KP; ++q) {
+      const int k = tid + q * NT;
+      nA[q] = nB[q] = nC[q] = nD[q] = T(0);
+      if (k < p) {
+        const int km = k - st, kp = k + st;
+        nB[q] = sB[k];
+        nD[q] = sD[k];
+        if (km >= 0) {
+          const T al = -sA[k] / sB[km];
+          nA[q] = al * sA[km];
+          nB[q] += al * sC[km];
+          nD[q] += al * sD[km];
+        }
+        if (kp < p) {
+          const T ga = -sC[k] / sB[kp];
+          nC[q] = ga * sC[kp];
+          nB[q] += ga * sA[kp];
+          nD[q] += ga * sD[kp];
+        }
       }
     }
     __syncthreads();
-    if (tid < p) {
-      sA[tid] = nA;
-      sB[tid] = nB;
-      sC[tid] = nC;
-      sD[tid] = nD;
+#pragma unroll
+    for (int q = 0; q < KP; ++q) {
+      const int k = tid + q * NT;
+      if (k < p) {
+        sA[k] = nA[q];
+        sB[k] = nB[q];
+        sC[k] = nC[q];
+        sD[k] = nD[q];
+      }
     }
     __syncthreads();
   }
-  if (tid < p) sD[tid] = sD[tid] / sB[tid];   // X_k
+  for (int k = tid; k < p; k += NT) sD[k] = sD[k] / sB[k];   // X_k
   __syncthreads();
   for (int i = tid; i < n; i += NT) {
     int k = (int)(((long)i * p) / n);
@@ -850,6 +865,12 @@ __device__ __forceinline__ void apply_one(const Args& a, const Inst& I, Shm<NT>&
   }
 }
 
+// Waves per SIMD the kernel is compiled for.  The workgroup's LDS (Shm, about
+// 81 KB at 512 threads) admits one workgroup per CU, i.e. two waves per SIMD
+// at 512 threads, so the register budget is that of two waves (256 VGPRs):
+// asking for more waves would only cap the registers and spill.
+constexpr int BATCH_WAVES_PER_EU = 2;
+
 // Persistent kernel: workgroups take instances from the ticket queue until
 // it runs dry (every workgroup reaches the exit).  Every device function of
 // the engine is inlined into this one kernel: the build with out-of-line
@@ -857,7 +878,7 @@ __device__ __forceinline__ void apply_one(const Args& a, const Inst& I, Shm<NT>&
 // 8) that the same source at -O1, the inlined build and a bounds-checked CPU
 // emulation do not show.
 template <int NT, int RAD>
-__global__ void __launch_bounds__(NT, NT / 128) batch_kernel(Args a) {
+__global__ void __launch_bounds__(NT, BATCH_WAVES_PER_EU) batch_kernel(Args a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Shm<NT>& sh = *reinterpret_cast<Shm<NT>*>(smem_raw);
   for (;;) {

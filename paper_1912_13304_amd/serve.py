@@ -37,6 +37,12 @@ class Result:
     inner_iters: List[int] = field(default_factory=list)
     relres: List[float] = field(default_factory=list)
     u: Optional[object] = None   # final state (device tensor) when keep_state
+    status: int = 0              # fde status of the failed call (0: every step solved)
+    error: str = ""              # its message
+
+    @property
+    def ok(self) -> bool:
+        return self.status == 0
 
     @property
     def latency(self) -> float:
@@ -172,6 +178,10 @@ class Server:
                 res = Result(prob.name, arr, start, self.now(), prob.steps,
                              [i.iters for i in infos], [i.inner_iters for i in infos],
                              [i.relres_true for i in infos], u)
+            except Exception as e:   # a failed request is reported; the slot keeps serving
+                stream.synchronize()
+                status = e.status if isinstance(e, fde.FdeError) else fde.FDE_EINVAL
+                res = Result(prob.name, arr, start, self.now(), prob.steps, status=status, error=str(e))
             finally:
                 self._release(need)
             with self.cv:
@@ -194,10 +204,13 @@ def serve_stream(arrivals, slots: int = 4, hbm_budget: float = 64e9, keep_state:
 
 
 def latency_stats(results) -> dict:
+    """Latency percentiles and throughput over the completed requests; failed
+    requests are counted separately and contribute no solves."""
     import numpy as np
-    lat = np.array([r.latency for r in results])
-    solves = sum(r.steps for r in results)
-    span = max(r.finish for r in results) - min(r.arrival for r in results)
-    return {"requests": len(results), "solves": solves, "p50_ms": float(1e3 * np.percentile(lat, 50)),
-            "p99_ms": float(1e3 * np.percentile(lat, 99)), "mean_ms": float(1e3 * lat.mean()),
-            "solves_per_s": solves / span if span > 0 else 0.0}
+    done = [r for r in results if r.ok]
+    lat = np.array([r.latency for r in done]) if done else np.zeros(1)
+    solves = sum(r.steps for r in done)
+    span = (max(r.finish for r in results) - min(r.arrival for r in results)) if results else 0.0
+    return {"requests": len(results), "failed": len(results) - len(done), "solves": solves,
+            "p50_ms": float(1e3 * np.percentile(lat, 50)), "p99_ms": float(1e3 * np.percentile(lat, 99)),
+            "mean_ms": float(1e3 * lat.mean()), "solves_per_s": solves / span if span > 0 else 0.0}

@@ -53,16 +53,30 @@ def rounding_spread(p, prec="tau", dside="left", restart=30, tol=1e-8):
     return relerr(xp, xo)
 
 
-def check_fp64(p, xg, ig, prec="tau", dside="left", restart=30, tol=1e-8):
+def check_fp64(p, xg, ig, prec="tau", dside="left", restart=30, tol=1e-8, gpu_kw=None):
+    """Mirror parity of one batched instance: iteration counts within one;
+    the iterates at equal step count (the side that ran one step longer is
+    rerun with the other's count; an instance's result does not depend on the
+    rest of the batch, so the GPU rerun is a batch of one) within 1e-10, or,
+    where the instance's conditioning amplifies rounding past that, within ten
+    times the distance the oracle's own iterate moves under a matrix-vector
+    product perturbed by FFT-sized rounding (rounding_spread), capped at 1e-8."""
+    fde = need_gpu()
     s, b, xo, io = oracle_solve(p, prec, dside, restart, tol)
     assert ig.converged and io["converged"], (p.name, ig.as_dict())
-    assert abs(ig.iters - io["iters"]) <= 1, (p.n, ig.iters, io["iters"])
+    d = ig.iters - io["iters"]
+    assert abs(d) <= 1, (p.n, ig.iters, io["iters"])
     assert relerr(s.matvec(xg), b) <= tol * (1 + 1e-6)
-    if ig.iters == io["iters"]:
-        err = relerr(xg, xo)
-        # 1e-10, or ten times the oracle's own spread under FFT-sized rounding
-        # differences where the system amplifies them past that
-        bound = 1e-10 if err < 1e-10 else max(1e-10, 10.0 * rounding_spread(p, prec, dside, restart, tol))
+    if d > 0:
+        kw = dict(gpu_kw or {}, dside=fde.D_LEFT if dside == "left" else fde.D_RIGHT, restart=restart, tol=tol)
+        (xg,), (ig2,) = batch_solve([p], fde, maxit=io["iters"], allow_notconv=True, **kw)
+        assert ig2.iters == io["iters"]
+    elif d < 0:
+        P = pc.make(prec, s, dside=dside)
+        xo, _ = krylov.fgmres(s.matvec, b, P, x0=p.u0, restart=restart, tol=tol, maxit=ig.iters)
+    err = relerr(xg, xo)
+    if err >= 1e-10:
+        bound = min(1e-8, max(1e-10, 10.0 * rounding_spread(p, prec, dside, restart, tol)))
         assert err < bound, (p.n, err, bound)
 
 
@@ -72,11 +86,11 @@ SIZES_SMALL = [1, 2, 3, 5, 7, 8, 15, 100, 255, 256, 1000, 1023]
 SIZES_LARGE = [2047, 3000, 4095, 5000, 8191, 12345]
 
 
-def batch_solve(problems, fde, **kw):
+def batch_solve(problems, fde, allow_notconv=False, **kw):
     with fde.Batch(problems, **kw) as bt:
         b = bt.pack([FDESystem.from_problem(p).rhs(p.u0) for p in problems])
         x = bt.pack([p.u0 for p in problems])
-        infos = bt.solve(b, x)
+        infos = bt.solve(b, x, allow_notconv=allow_notconv)
         return bt.unpack(x), infos
 
 
@@ -120,14 +134,7 @@ def test_batch_preconditioners(prec):
         probs.append(p)
     xs, infos = batch_solve(probs, fde, prec=code, maxit=20000)
     for p, xg, ig in zip(probs, xs, infos):
-        s, b, xo, io = oracle_solve(p, prec)
-        assert ig.converged and io["converged"]
-        # long unpreconditioned runs may drift by a few restarts' worth of rounding
-        assert abs(ig.iters - io["iters"]) <= max(1, 0.005 * io["iters"]), (p.n, ig.iters, io["iters"])
-        assert relerr(s.matvec(xg), b) <= 1e-8 * (1 + 1e-6)
-        if ig.iters == io["iters"]:
-            err = relerr(xg, xo)
-            assert err < 1e-10 or err < 10.0 * rounding_spread(p, prec), (p.n, err)
+        check_fp64(p, xg, ig, prec=prec, gpu_kw=dict(prec=code, maxit=20000))
 
 
 @pytest.mark.parametrize("variant", [
@@ -160,8 +167,10 @@ def test_batch_mixed(prec):
         for p, xg, ig in zip(probs, xs, infos):
             s, b, xo, io = oracle_solve(p, prec)
             assert ig.converged
-            assert relerr(s.matvec(xg), b) <= 1e-8 * (1 + 1e-6)   # float64 true residual, by the oracle
-            assert relerr(xg, xo) < 1e-6
+            rg, ro = b - s.matvec(xg), b - s.matvec(xo)
+            assert np.linalg.norm(rg) <= 1e-8 * (1 + 1e-6) * np.linalg.norm(b)   # float64 true residual
+            # Varah: every row of the first-order M is diagonally dominant by nu
+            assert np.abs(xg - xo).max() <= (np.abs(rg).max() + np.abs(ro).max()) / s.nu
 
 
 def test_batch_alone_equals_mix():
@@ -196,14 +205,18 @@ def test_batch_run_graph_matches_eager():
         ue2 = ue.clone()
         bt.run(ue2, 1, use_graph=False)
         assert torch.equal(ug2, ue2)
-        xs = bt.unpack(ug)
-    # the state after `steps` implicit steps, by the oracle (same solver, x0 = u)
-    for p, xg in zip(probs, xs):
-        s = FDESystem.from_problem(p)
-        u = p.u0.copy()
-        for _ in range(steps):
-            u, io = krylov.fgmres(s.matvec, s.rhs(u), pc.make("tau", s), x0=u, restart=30, tol=1e-8)
-        assert relerr(xg, u) < 1e-7
+        # every step against the oracle's step from the GPU's previous state
+        us = bt.pack([p.u0 for p in probs])
+        prev = bt.unpack(us)
+        for step in range(steps):
+            info = bt.run(us, 1, use_graph=True)[0]
+            cur = bt.unpack(us)
+            for p, u0, xg, ig in zip(probs, prev, cur, info):
+                q = fi.variable_1d(n=p.n[0], alpha=p.alpha[0], steps=1)
+                q.dplus, q.dminus, q.u0 = p.dplus, p.dminus, u0
+                check_fp64(q, xg, ig)
+            prev = cur
+        assert torch.equal(us, ug)
 
 
 def test_batch_operators_disabled():
@@ -306,3 +319,23 @@ def test_batch_operators(variant, prec):
                 assert relerr(yv, s.matvec(xv)) < tol, (p.n, precision, "matvec", relerr(yv, s.matvec(xv)))
                 zo = pc.make(prec, s)(xv)
                 assert relerr(zv, zo) < tol, (p.n, precision, "tau", relerr(zv, zo))
+
+
+def test_batched_workload_sample_against_oracle():
+    """The 512-instance batched workload (n log-uniform in [255, 16383],
+    alpha ~ U(1.1, 1.9), scaled Example 1 coefficients), first time step in
+    float64 in one launch: a sample of 12 instances spread over the sizes is
+    mirrored by the oracle, and every instance's float64 true residual is
+    within the tolerance."""
+    fde = need_gpu()
+    probs = fi.batched_1d(count=512, steps=1)
+    with fde.Batch(probs, maxit=20000) as bt:
+        u = bt.pack([p.u0 for p in probs])
+        infos = bt.run(u, 1)[0]
+        xs = bt.unpack(u)
+    assert all(i.converged for i in infos)
+    assert max(i.relres_true for i in infos) <= 1e-8
+    order = np.argsort([p.n[0] for p in probs])
+    for k in np.linspace(0, len(probs) - 1, 12).astype(int):
+        i = int(order[k])
+        check_fp64(probs[i], xs[i], infos[i])

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import fde_inputs as fi
-from gpu_util import dev, host, need_gpu, relerr, torch
+from gpu_util import dev, host, mirror_check, need_gpu, relerr, torch
 from oracle import krylov, precond as pc
 from oracle.system import FDESystem
 
@@ -33,27 +33,40 @@ def test_big_matvec_and_tau(n, weights, time):
         assert relerr(host(b), s.rhs(x)) < 1e-12
 
 
-@pytest.mark.parametrize("alpha", [1.8, 1.5])
+@pytest.mark.parametrize("alpha", [1.8, 1.5, 1.2])
 def test_big_fgmres_full_size(alpha):
     """First implicit-Euler step of the 1D variable-coefficient workload,
-    n = 65535, GMRES(30) + P_F to 1e-8, mirrored by the oracle."""
+    n = 65535, GMRES(30) + P_F to 1e-8, mirrored by the oracle (iterations
+    within one, iterates at equal step count within 1e-10)."""
     fde = need_gpu()
     p = fi.variable_1d(n=65535, alpha=alpha)
     s = FDESystem.from_problem(p)
     b = s.rhs(p.u0)
-    xo, io = krylov.fgmres(s.matvec, b, pc.make("tau", s), x0=p.u0, restart=30, tol=1e-8)
+    P = pc.make("tau", s)
+
+    def orun(maxit):
+        x, info = krylov.fgmres(s.matvec, b, P, x0=p.u0, restart=30, tol=1e-8, maxit=maxit or 100000)
+        return x, info["iters"]
+
+    def grun(maxit):
+        with fde.Plan(p, maxit=maxit) as plan:
+            x = dev(p.u0)
+            info = plan.solve(dev(b), x, allow_notconv=True)
+            return host(x), info.iters
+
     with fde.Plan(p) as plan:
         x = dev(p.u0)
         ig = plan.solve(dev(b), x)
         xg = host(x)
-    assert ig.converged and io["converged"]
-    assert abs(ig.iters - io["iters"]) <= max(1, 0.005 * io["iters"]), (ig.iters, io["iters"])
+    assert ig.converged
+    mirror_check(xg, ig.iters, orun, grun)
     assert relerr(s.matvec(xg), b) <= 1e-8 * (1 + 1e-6)
-    if ig.iters == io["iters"]:
-        assert relerr(xg, xo) < 1e-10
 
 
 def test_big_mixed_full_size():
+    """Mixed form at n = 65535: float64 true residual within the tolerance
+    (recomputed by the oracle) and Varah's bound against the oracle's float64
+    solution (every row of the first-order M is diagonally dominant by nu)."""
     fde = need_gpu()
     p = fi.variable_1d(n=65535, alpha=1.5)
     s = FDESystem.from_problem(p)
@@ -64,5 +77,6 @@ def test_big_mixed_full_size():
         ig = plan.solve(dev(b), x)
         xg = host(x)
     assert ig.converged
-    assert relerr(s.matvec(xg), b) <= 1e-8 * (1 + 1e-6)   # FP64 true residual, checked by the oracle
-    assert relerr(xg, xo) < 1e-6
+    rg, ro = b - s.matvec(xg), b - s.matvec(xo)
+    assert np.linalg.norm(rg) <= 1e-8 * (1 + 1e-6) * np.linalg.norm(b)
+    assert np.abs(xg - xo).max() <= (np.abs(rg).max() + np.abs(ro).max()) / s.nu

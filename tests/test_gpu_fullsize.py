@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import fde_inputs as fi
-from gpu_util import dev, host, need_gpu, relerr, torch
+from gpu_util import dev, host, mirror_check, need_gpu, relerr, torch
 from oracle import krylov, precond as pc
 from oracle.system import FDESystem
 
@@ -84,3 +84,90 @@ def test_full_mixed_solve(full):
     assert infos[1].converged
     b2 = s.rhs(xs[0])
     assert np.linalg.norm(b2 - s.matvec(xs[1])) <= p.tol * (1 + 1e-6) * np.linalg.norm(b2)
+
+
+def _workers():
+    return min(16, len(os.sched_getaffinity(0)))
+
+
+def test_full_fp64_last_step_mirrors_oracle(full):
+    """The tenth implicit-Euler step of the job (the benchmark's step count),
+    mirrored by the oracle from the GPU's ninth state."""
+    fde = need_gpu()
+    p = fi.variable_2d(n=1023, steps=10)
+    s, P = full["s"], full["P"]
+    with fde.Plan(p, precision=fde.FP64) as plan:
+        u = dev(p.u0.reshape(-1))
+        bd = torch.empty(p.N, dtype=torch.float64, device="cuda")
+        for step in range(10):
+            prev = u.clone()
+            plan.rhs(u, bd)
+            x = u.clone()
+            info = plan.solve(bd, x)
+            u = x
+        xg, u9, b = host(u), host(prev), host(bd)
+        assert relerr(b, s.rhs(u9)) < 1e-12
+
+        def grun(maxit):
+            with fde.Plan(p, precision=fde.FP64, maxit=maxit) as q:
+                x = dev(u9)
+                i = q.solve(dev(b), x, allow_notconv=True)
+                return host(x), i.iters
+
+    def orun(maxit):
+        x, i = krylov.fgmres(s.matvec, b, P, x0=u9, restart=30, tol=p.tol, maxit=maxit or 100000)
+        return x, i["iters"]
+
+    assert info.converged
+    mirror_check(xg, info.iters, orun, grun)
+
+
+def test_full_cn_second_order_step():
+    """1023 x 1023, Crank-Nicolson with the second-order weights (Sections
+    1.3-1.4), P_F with the symbols q_a, q_b: one step mirrored by the oracle."""
+    fde = need_gpu()
+    p = fi.variable_2d(n=1023, steps=1)
+    p.weights, p.time = "weighted", "cn"
+    w = _workers()
+    s = FDESystem.from_problem(p, workers=w)
+    P = pc.make("tau", s, workers=w)
+    u0 = p.u0.reshape(-1)
+    b = s.rhs(u0)
+
+    def orun(maxit):
+        x, i = krylov.fgmres(s.matvec, b, P, x0=u0, restart=30, tol=p.tol, maxit=maxit or 100000)
+        return x, i["iters"]
+
+    def grun(maxit):
+        with fde.Plan(p, maxit=maxit) as q:
+            x = dev(u0)
+            i = q.solve(dev(b), x, allow_notconv=True)
+            return host(x), i.iters
+
+    with fde.Plan(p) as plan:
+        bd = torch.empty(p.N, dtype=torch.float64, device="cuda")
+        plan.rhs(dev(u0), bd)
+        assert relerr(host(bd), b) < 1e-12
+        x = dev(u0)
+        info = plan.solve(dev(b), x)
+        xg = host(x)
+    assert info.converged
+    mirror_check(xg, info.iters, orun, grun)
+
+
+def test_full_mixed_forward_error(full):
+    """Headline mixed form (float32 inner GMRES(16), float64 outer FGMRES(30))
+    at the outer tolerance the benchmark uses for the stated accuracy: relative
+    error <= 1e-8 against the step solved by the oracle to a true residual of
+    1e-12."""
+    fde = need_gpu()
+    from test_gpu_mixed import ACC_TOL
+    p, s, P, u0, b = full["p"], full["s"], full["P"], full["u0"], full["b"]
+    xr, ir = krylov.fgmres(s.matvec, b, P, x0=full["xo"], restart=30, tol=1e-12)
+    assert ir["converged"]
+    with fde.Plan(p, precision=fde.MIXED, inner_steps=16, tol=ACC_TOL) as plan:
+        x = dev(u0)
+        info = plan.solve(dev(b), x)
+        xg = host(x)
+    assert info.converged
+    assert relerr(xg, xr) <= 1e-8, relerr(xg, xr)

@@ -120,3 +120,34 @@ def test_mixed_probe_keeps_results():
     assert np.array_equal(res[0][0], res[1][0])
     ms, launches, by = res[1][2]
     assert launches > 0 and ms > 0 and by > 0
+
+
+# Outer tolerance at which the mixed form is run to meet the stated forward
+# error of 1e-8 against the oracle's float64 reference solution.
+ACC_TOL = 1e-9
+
+
+@pytest.mark.parametrize("case", ["1d-4095", "2d-255", "2d-127x63-right"])
+def test_mixed_forward_error_1e8(case):
+    """The mixed form's result is within 1e-8 (relative) of the exact
+    solution of the step, represented by the oracle's float64 FGMRES run to a
+    true residual of 1e-13, when its float64 outer loop stops at ACC_TOL."""
+    fde = need_gpu()
+    kw = {}
+    if case == "1d-4095":
+        p = fi.variable_1d(n=4095, alpha=1.45, seed=31, steps=1)
+        x0 = p.u0
+    else:
+        n1, n2 = (255, 255) if case == "2d-255" else (127, 63)
+        p = fi.variable_2d(n=n1, n2=n2, seed=32, steps=1)
+        x0 = p.u0.reshape(-1)
+        if case.endswith("right"):
+            kw["dside"] = fde.D_RIGHT
+    s = FDESystem.from_problem(p)
+    b = s.rhs(x0)
+    P = pc.make("tau", s, dside="right" if kw else "left")
+    xr, ir = krylov.fgmres(s.matvec, b, P, x0=x0, restart=30, tol=1e-13)
+    assert ir["converged"]
+    xg, info = mixed_solve(fde, p, b, x0, inner_steps=16, tol=ACC_TOL, **kw)
+    assert info.converged and info.relres_true <= ACC_TOL
+    assert relerr(xg, xr) <= 1e-8, relerr(xg, xr)

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import fde_inputs as fi
-from gpu_util import dev, host, need_gpu, relerr, torch
+from gpu_util import dev, host, mirror_check, need_gpu, relerr, torch
 from oracle import krylov, precond as pc
 from oracle.system import FDESystem
 
@@ -76,9 +76,12 @@ def test_tau_1d(n, dside):
 
 @pytest.mark.parametrize("n1,n2", SHAPES_2D)
 @pytest.mark.parametrize("dside", ["left", "right"])
-def test_tau_2d(n1, n2, dside):
+@pytest.mark.parametrize("weights", ["shifted", "weighted"])
+def test_tau_2d(n1, n2, dside, weights):
+    """2D P_F: symbol p_a (first-order weights) or q_a (second-order weights,
+    eq. second_order_symbol) sampled on both axes, with D on either side."""
     fde = need_gpu()
-    p = prob2d(n1, n2)
+    p = prob2d(n1, n2, weights=weights, time="cn" if weights == "weighted" else "euler")
     s = FDESystem.from_problem(p)
     P = pc.make("tau", s, dside=dside)
     v = rng_vec(s.N, 5 * n1 + n2)
@@ -158,11 +161,33 @@ def oracle_solve(p, b, x0, dside="left", restart=30, tol=1e-8, solver="gmres"):
     return krylov.fgmres(s.matvec, b, P, x0=x0, restart=restart, tol=tol)
 
 
-def gpu_solve(fde, p, b, x0, **kw):
+def gpu_solve(fde, p, b, x0, allow_notconv=False, **kw):
     with fde.Plan(p, **kw) as plan:
         x = dev(x0)
-        info = plan.solve(dev(b), x)
+        info = plan.solve(dev(b), x, allow_notconv=allow_notconv)
         return host(x), info
+
+
+def mirror(fde, p, b, x0, xg, ig, kind="tau", dside="left", restart=30, tol=1e-8, gpu_kw=None):
+    """mirror_check for an FGMRES solve: the oracle's build-mode FGMRES with
+    preconditioner `kind`, and a GPU rerun with an iteration cap."""
+    s = FDESystem.from_problem(p)
+    P = pc.make(kind, s, dside=dside)
+    gk = dict(gpu_kw or {})
+
+    def orun(maxit):
+        x, info = krylov.fgmres(s.matvec, b, P, x0=x0, restart=restart, tol=tol,
+                                maxit=maxit if maxit else 100000)
+        if not maxit:
+            assert info["converged"]
+        return x, info["iters"]
+
+    def grun(maxit):
+        x, info = gpu_solve(fde, p, b, x0, allow_notconv=True, maxit=maxit, restart=restart, **gk)
+        assert info.iters == maxit
+        return x, info.iters
+
+    return mirror_check(xg, ig.iters, orun, grun)
 
 
 @pytest.mark.parametrize("n,alpha,restart", [(7, 1.5, 30), (63, 1.2, 30), (255, 1.5, 30), (1023, 1.8, 30),
@@ -173,11 +198,9 @@ def test_fgmres_1d(n, alpha, restart):
     p = fi.variable_1d(n=n, alpha=alpha, seed=n)
     s = FDESystem.from_problem(p)
     b = s.rhs(p.u0)
-    xo, io = oracle_solve(p, b, p.u0, restart=restart)
     xg, ig = gpu_solve(fde, p, b, p.u0, restart=restart)
-    assert ig.converged and io["converged"]
-    assert abs(ig.iters - io["iters"]) <= 1, (ig.iters, io["iters"])
-    assert relerr(xg, xo) < 1e-10
+    assert ig.converged
+    mirror(fde, p, b, p.u0, xg, ig, restart=restart)
     assert ig.relres_true <= 1e-8
     assert relerr(s.matvec(xg), b) <= 1e-8 * (1 + 1e-6)
 
@@ -190,29 +213,93 @@ def test_fgmres_2d(n1, n2, dside):
     s = FDESystem.from_problem(p)
     b = s.rhs(p.u0.reshape(-1))
     x0 = p.u0.reshape(-1)
-    xo, io = oracle_solve(p, b, x0, dside=dside)
-    xg, ig = gpu_solve(fde, p, b, x0, dside=fde.D_LEFT if dside == "left" else fde.D_RIGHT)
-    assert ig.converged and io["converged"]
-    assert abs(ig.iters - io["iters"]) <= 1, (ig.iters, io["iters"])
-    assert relerr(xg, xo) < 1e-10
+    dk = dict(dside=fde.D_LEFT if dside == "left" else fde.D_RIGHT)
+    xg, ig = gpu_solve(fde, p, b, x0, **dk)
+    assert ig.converged
+    mirror(fde, p, b, x0, xg, ig, dside=dside, gpu_kw=dk)
     assert relerr(s.matvec(xg), b) <= 1e-8 * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("n1,n2", [(15, 15), (63, 63), (255, 255), (127, 31)])
+def test_fgmres_2d_cn_second_order(n1, n2):
+    """2D Crank-Nicolson with the second-order weights (Sections 1.3-1.4,
+    eq. coef:2d): one step of the headline coefficient fields, P_F with the
+    symbol q_a (eq. second_order_symbol), mirrored by the oracle."""
+    fde = need_gpu()
+    p = prob2d(n1, n2, weights="weighted", time="cn", seed=n1 * 3 + n2)
+    s = FDESystem.from_problem(p)
+    x0 = p.u0.reshape(-1)
+    b = s.rhs(x0)
+    xg, ig = gpu_solve(fde, p, b, x0)
+    assert ig.converged
+    mirror(fde, p, b, x0, xg, ig)
+    assert relerr(s.matvec(xg), b) <= 1e-8 * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("example", [2, 3])
+@pytest.mark.parametrize("n", [15, 31])
+def test_paper_examples_2d_steps(example, n):
+    """Examples 2 and 3 of Section 4 (second-order weights, Crank-Nicolson,
+    h_t = 1/n, the paper's source term) on the GPU: every step's right-hand
+    side and solve mirror the oracle from the GPU's previous state (P_F with D
+    on the right, as Tables 3-4, GMRES tolerance 1e-7, x0 = u^{m-1}); the
+    error at T = 1 falls by about four per halving of h (second order)."""
+    fde = need_gpu()
+    p = fi.paper_2d(n, example)
+    s = FDESystem.from_problem(p)
+    X, Y = p.meta["X"], p.meta["Y"]
+    a, bt = p.alpha
+    u = p.u0.reshape(-1)
+    dk = dict(dside=fde.D_RIGHT, tol=p.tol)
+    with fde.Plan(p, **dk) as plan:
+        bd = torch.empty(p.N, dtype=torch.float64, device="cuda")
+        for m in range(1, p.steps + 1):
+            f = fi.example23_source(X, Y, (m - 0.5) * p.dt, a, bt).reshape(-1)
+            plan.rhs(dev(u), bd, f=dev(f))
+            b = host(bd)
+            assert relerr(b, s.rhs(u, f)) < 1e-12
+            x = dev(u)
+            ig = plan.solve(bd, x)
+            xg = host(x)
+            if m in (1, p.steps // 2, p.steps):
+                mirror(fde, p, b, u, xg, ig, dside="right", tol=p.tol, gpu_kw=dk)
+            u = xg
+    err = np.abs(u - fi.example23_exact(X, Y, p.steps * p.dt).reshape(-1)).max()
+    # max error at T = 1 of the second-order scheme (Section 4): 1.0e-1 at n = 15, 2.6e-2 at n = 31
+    assert err < {15: 0.12, 31: 0.03}[n], err
 
 
 def test_fgmres_many_restarts():
     """GMRES(5) on n = 4095, alpha = 1.3 needs about a thousand iterations
-    (over 200 restarts).  Rounding differences between two FP64 orders of
-    evaluation move the stopping point by a few iterations there; the counts
-    must agree to 0.5% and both solutions must meet the tolerance."""
+    (over 200 restarts).  The two sides follow the same iterates: after a
+    fixed number of steps (no early stop) they agree to 1e-10.  Where the
+    residual curve flattens near the tolerance, a rounding-level change of the
+    input moves the stopping step of the oracle itself by several steps; the
+    stopping steps are compared against that measured spread, and the final
+    solutions against Varah's bound (every row of M is diagonally dominant by
+    at least nu), which holds for any two solutions meeting the tolerance."""
     fde = need_gpu()
     p = fi.variable_1d(n=4095, alpha=1.3, seed=4095)
     s = FDESystem.from_problem(p)
     b = s.rhs(p.u0)
+    P = pc.make("tau", s)
+    for k in (25, 100):
+        xo, io = krylov.fgmres(s.matvec, b, P, x0=p.u0, restart=5, tol=1e-300, maxit=k)
+        xg, ig = gpu_solve(fde, p, b, p.u0, allow_notconv=True, restart=5, tol=1e-300, maxit=k)
+        assert ig.iters == io["iters"] == k
+        assert relerr(xg, xo) < 1e-10, (k, relerr(xg, xo))
     xo, io = oracle_solve(p, b, p.u0, restart=5)
     xg, ig = gpu_solve(fde, p, b, p.u0, restart=5)
     assert ig.converged and io["converged"]
-    assert abs(ig.iters - io["iters"]) <= max(1, 0.005 * io["iters"]), (ig.iters, io["iters"])
-    assert relerr(s.matvec(xg), b) <= 1e-8 * (1 + 1e-6)
-    assert relerr(xg, xo) < 1e-6
+    its = []
+    for seed in range(3):
+        e = np.random.default_rng(seed).uniform(-1, 1, b.size) * 2.0 ** -52
+        its.append(krylov.fgmres(s.matvec, b * (1 + e), P, x0=p.u0, restart=5, tol=1e-8)[1]["iters"])
+    spread = max(abs(i - io["iters"]) for i in its)
+    assert abs(ig.iters - io["iters"]) <= max(1, spread), (ig.iters, io["iters"], its)
+    rg, ro = b - s.matvec(xg), b - s.matvec(xo)
+    assert np.linalg.norm(rg) <= 1e-8 * (1 + 1e-6) * np.linalg.norm(b)
+    assert np.abs(xg - xo).max() <= (np.abs(rg).max() + np.abs(ro).max()) / s.nu
 
 
 def test_pcg_constant_1d_full_size():
@@ -234,8 +321,8 @@ def const_problem(n, alpha, d):
     return p
 
 
-@pytest.mark.parametrize("n,alpha", [(7, 1.5), (15, 1.9), (63, 1.2), (511, 1.7), (2047, 1.5), (4095, 1.3),
-                                     (8191, 1.5)])
+@pytest.mark.parametrize("n,alpha", [(7, 1.5), (15, 1.9), (31, 1.5), (63, 1.2), (127, 1.6), (511, 1.7),
+                                     (2047, 1.5), (4095, 1.3), (8191, 1.5)])
 @pytest.mark.parametrize("d", [1.0, 1.3])
 def test_pcg_constant_1d_sizes(n, alpha, d):
     """PCG + P_F on constant coefficients from a nonzero start, to 1e-10.
@@ -380,16 +467,10 @@ def test_tri_fgmres(n, alpha):
     p = prob1d(n, alpha=alpha, seed=n)
     s = FDESystem.from_problem(p)
     b = s.rhs(p.u0)
-    xo, io = krylov.fgmres(s.matvec, b, pc.make("tri", s), x0=p.u0, restart=30, tol=1e-8)
-    with fde.Plan(p, prec=fde.P_TRI) as plan:
-        x = dev(p.u0)
-        ig = plan.solve(dev(b), x)
-        xg = host(x)
-    assert ig.converged and io["converged"]
-    assert abs(ig.iters - io["iters"]) <= max(1, 0.005 * io["iters"]), (ig.iters, io["iters"])
+    xg, ig = gpu_solve(fde, p, b, p.u0, prec=fde.P_TRI)
+    assert ig.converged
+    mirror(fde, p, b, p.u0, xg, ig, kind="tri", gpu_kw=dict(prec=fde.P_TRI))
     assert relerr(s.matvec(xg), b) <= 1e-8 * (1 + 1e-6)
-    if ig.iters == io["iters"]:
-        assert relerr(xg, xo) < 1e-9
 
 
 def test_tri_mixed():

@@ -60,3 +60,22 @@ def test_admission_budget():
     assert peak[0] <= budget
     st = serve.latency_stats(srv.results)
     assert st["p99_ms"] >= st["p50_ms"] > 0
+
+
+def test_failed_request_is_reported_and_slot_survives():
+    """A request the library rejects (a negative coefficient: FDE_EINVAL at
+    assembly) comes back as a failed result; the slot's worker keeps serving
+    and every other request completes."""
+    fde = need_gpu()
+    from paper_1912_13304_amd import serve
+    arr = small_stream(count=6, seed=9)
+    bad = arr[2].problem
+    bad.dplus = bad.dplus.copy()
+    bad.dplus.reshape(-1)[1] = -1.0
+    results, _ = serve.serve_stream(arr, slots=2)
+    assert len(results) == len(arr)
+    by = {r.name: r for r in results}
+    assert not by[bad.name].ok and by[bad.name].status == fde.FDE_EINVAL
+    assert all(r.ok for r in results if r.name != bad.name)
+    st = serve.latency_stats(results)
+    assert st["failed"] == 1 and st["requests"] == len(arr)

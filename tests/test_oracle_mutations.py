@@ -60,3 +60,53 @@ def test_symbol_scale_error_is_caught_by_closed_form():
 def test_wrong_diagonal_side_is_caught():
     s, _ = ex.ex1_system(63, 1.5)
     assert abs(ex.kappa(s, "tau", "left") - PIN_PF) > 0.05
+
+
+def _theorem3_holds():
+    """The inclusion of Theorem 3 on one 2D constant-coefficient case with
+    d != e and alpha != beta (helpers of test_oracle_tau_hat_2d)."""
+    from test_oracle_tau_hat_2d import const_2d, gen_eigs, p_hat_dense, split_1d
+    s = const_2d(15, 11, 1.8, 1.2, 1.0, 7.0)
+    A1, A2, P1, P2 = split_1d(s, 1.0, 7.0)
+    l1, l2 = gen_eigs(A1, P1), gen_eigs(A2, P2)
+    lo, hi = min(l1.min(), l2.min()), max(l1.max(), l2.max())
+    lam = gen_eigs(s.dense(), p_hat_dense(s))
+    return lam.min() >= lo * (1 - 1e-10) and lam.max() <= hi * (1 + 1e-10)
+
+
+def _mutate_tau_hat(monkeypatch, build):
+    from oracle import precond as pc
+    orig = pc.TauHatPreconditioner.__init__
+
+    def init(self, sysm, workers=None):
+        orig(self, sysm, workers)
+        fx = symbol.F_symbol(sysm.alpha[0], symbol.theta(sysm.n[0]), sysm.weights)
+        fy = symbol.F_symbol(sysm.alpha[1], symbol.theta(sysm.n[1]), sysm.weights)
+        d, e = float(sysm.dplus.flat[0]), float(sysm.eplus.flat[0])
+        self.F = build(sysm, fx, fy, d, e)
+    monkeypatch.setattr(pc.TauHatPreconditioner, "__init__", init)
+
+
+def test_p_hat_unmutated_satisfies_theorem3():
+    assert _theorem3_holds()
+
+
+def test_p_hat_dropped_kappa_is_caught(monkeypatch):
+    _mutate_tau_hat(monkeypatch, lambda s, fx, fy, d, e: s.nu + d * fx[None, :] + e * fy[:, None])
+    assert not _theorem3_holds()
+
+
+def test_p_hat_swapped_coefficients_are_caught(monkeypatch):
+    _mutate_tau_hat(monkeypatch, lambda s, fx, fy, d, e: s.nu + e * fx[None, :] + s.kappa * d * fy[:, None])
+    assert not _theorem3_holds()
+
+
+def test_p_hat_swapped_axes_are_caught(monkeypatch):
+    # the x-direction samples laid along y and vice versa (square grid so the shapes agree)
+    from test_oracle_tau_hat_2d import const_2d, gen_eigs, p_hat_dense, split_1d
+    _mutate_tau_hat(monkeypatch, lambda s, fx, fy, d, e: s.nu + d * fx[:, None] + s.kappa * e * fy[None, :])
+    s = const_2d(15, 15, 1.8, 1.2, 1.0, 7.0)
+    A1, A2, P1, P2 = split_1d(s, 1.0, 7.0)
+    l1, l2 = gen_eigs(A1, P1), gen_eigs(A2, P2)
+    lam = gen_eigs(s.dense(), p_hat_dense(s))
+    assert lam.min() < min(l1.min(), l2.min()) * (1 - 1e-6) or lam.max() > max(l1.max(), l2.max()) * (1 + 1e-6)
