@@ -262,6 +262,28 @@ fde_status fde_batch_set_cfg(fde_batch batch, const fde_batch_cfg* cfg);
 /* Releases the batch (synchronises the device first). NULL is ignored. */
 void fde_batch_destroy(fde_batch batch);
 
+/* ---------------------------------------------------------------------------
+ * Allocation-free solve, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  One call does what fde_assemble + fde_solve + fde_destroy do
+ * for a 1D float64 PCG plan (dim = 1, solver = FDE_S_PCG, precision =
+ * FDE_FP64, prec = FDE_P_TAU, FDE_P_TAU_HAT or FDE_P_TILDE) whose line fits
+ * one workgroup: 8 <= n + 1 <= 4096, n + 1 a power of two.  It runs the same
+ * set-up arithmetic and the same kernels, so its result equals that of the
+ * plan path.  Every device table and work vector lives in one static device
+ * array of 512 KiB that the library holds on each device it runs on until the
+ * process ends; the call makes no hipMalloc/hipFree and no other device
+ * allocation (its host-side set-up uses ordinary host memory).
+ *   dplus, dminus, b: device, length n; read in place (not copied).
+ *   x: device, length n: the starting vector on entry, the solution on return.
+ *   info: host pointer or NULL.
+ * Synchronises `stream`.  Errors as fde_assemble and fde_solve;
+ * FDE_EUNSUPPORTED for any other configuration or size.  Calls that overlap
+ * on one device share the static array and race: issue them one at a time
+ * per device. */
+fde_status fde_pcg1d_solve_noalloc(const fde_params* p, const double* dplus, const double* dminus,
+                                   const double* b, double* x, fde_info* info, void* stream);
+
 /* Thread-local description of the last error, "" when none. */
 const char* fde_last_error(void);
 

@@ -16,6 +16,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -233,10 +234,11 @@ static fde_status upload_cx(fde_plan pl, cx<T>** dst, const std::vector<std::com
 // Twiddles W2[m] = exp(-i pi m/P), m < 2P, and circulant eigenvalues of the
 // 2P x 2P circulant whose leading n x n block is T (or S): first column
 // (-g_1, ..., -g_n, 0, ..., 0, -g_0).
-static fde_status direction_tables(fde_plan pl, double alpha, int n, cx<double>** W2d, cx<float>** W2f,
-                                   cx<double>** lamd, cx<float>** lamf) {
+static void direction_host(double alpha, int n, int kind, std::vector<std::complex<double>>& W2,
+                           std::vector<std::complex<double>>& lam) {
   const int P = n + 1;
-  std::vector<std::complex<double>> W2(2 * P), lam(2 * P, 0.0);
+  W2.assign(2 * P, 0.0);
+  lam.assign(2 * P, 0.0);
   for (int m = 0; m < 2 * P; ++m) {
     // angle pi m/P, reduced by symmetry to keep the argument small
     const double t = (double)m / (double)P;  // exact
@@ -247,11 +249,17 @@ static fde_status direction_tables(fde_plan pl, double alpha, int n, cx<double>*
     const int q = (int)((2L * m) / P) & 3;
     if ((2L * m) % P == 0) W2[m] = q == 0 ? 1.0 : q == 1 ? std::complex<double>(0, -1) : q == 2 ? -1.0 : std::complex<double>(0, 1);
   }
-  std::vector<double> g = weights(alpha, n, pl->p.weights);
+  std::vector<double> g = weights(alpha, n, kind);
   for (int k = 0; k < n; ++k) lam[k] = -g[k + 1];
   lam[2 * P - 1] = -g[0];
   host_fft(lam);
   lam.resize(P + 1);
+}
+
+static fde_status direction_tables(fde_plan pl, double alpha, int n, cx<double>** W2d, cx<float>** W2f,
+                                   cx<double>** lamd, cx<float>** lamf) {
+  std::vector<std::complex<double>> W2, lam;
+  direction_host(alpha, n, pl->p.weights, W2, lam);
   TRY(upload_cx(pl, W2d, W2));
   TRY(upload_cx(pl, W2f, W2));
   TRY(upload_cx(pl, lamd, lam));
@@ -1510,6 +1518,174 @@ extern "C" fde_status fde_solve(fde_plan pl, const double* b, double* x, fde_inf
   auto t0 = std::chrono::steady_clock::now();
   fde_status s = pl->p.solver == FDE_S_PCG ? solve_pcg(pl, b, x, info, (hipStream_t)stream)
                                            : solve_gmres(pl, b, x, info, (hipStream_t)stream);
+  if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free one-shot 1D PCG solve (fde_pcg1d_solve_noalloc)
+//
+// The same set-up arithmetic and the same one-workgroup PCG kernel as
+// fde_assemble + fde_solve for a 1D PCG plan whose line fits one workgroup,
+// with every device table and work vector in one static device array instead
+// of plan buffers.  The coefficient arrays are read where the caller keeps
+// them.  Nothing in the array needs to start at zero: every entry is written
+// before it is read in the same call.
+// ---------------------------------------------------------------------------
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)512 << 10;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[NOALLOC_MAX_DEVICES];   // device address of `scratch`, per device
+
+// Device address of `scratch` on the current device, looked up once per device
+// (each device holds its own copy at its own address).
+static fde_status scratch_address(unsigned char** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+    return fail(FDE_EUNSUPPORTED, "device %d: the allocation-free entry point handles devices 0..%d", dev,
+                NOALLOC_MAX_DEVICES - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(FDE_EHIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+  return FDE_OK;
+}
+
+struct NoallocLayout {
+  size_t stats, dinv, dinvf, fx, fzero, W2, lam, vec, ks, total;
+};
+
+static NoallocLayout noalloc_layout(int n, long ld) {
+  auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+  const size_t P = (size_t)n + 1;
+  NoallocLayout L{};
+  size_t o = 0;
+  L.stats = o;  o = up(o + (3 + 3 * 256) * sizeof(double));
+  L.dinv = o;   o = up(o + (size_t)n * sizeof(double));
+  L.dinvf = o;  o = up(o + (size_t)n * sizeof(float));
+  L.fx = o;     o = up(o + (size_t)n * sizeof(double));
+  L.fzero = o;  o = up(o + sizeof(double));
+  L.W2 = o;     o = up(o + 2 * P * sizeof(cx<double>));
+  L.lam = o;    o = up(o + (P + 1) * sizeof(cx<double>));
+  L.vec = o;    o = up(o + 4 * (size_t)ld * sizeof(double));   // r, p, q, z
+  L.ks = o;     o = up(o + sizeof(KState));
+  L.total = o;
+  return L;
+}
+
+extern "C" fde_status fde_pcg1d_solve_noalloc(const fde_params* p, const double* dplus, const double* dminus,
+                                              const double* b, double* x, fde_info* info, void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!dplus || !dminus || !b || !x) return fail(FDE_EINVAL, "NULL argument");
+  TRY(validate(p));
+  if (p->dim != 1 || p->solver != FDE_S_PCG || p->precision != FDE_FP64)
+    return fail(FDE_EUNSUPPORTED, "the allocation-free solve is the 1D float64 PCG (dim = 1, FDE_S_PCG, FDE_FP64)");
+  if (p->prec != FDE_P_TAU && p->prec != FDE_P_TAU_HAT && p->prec != FDE_P_TILDE)
+    return fail(FDE_EUNSUPPORTED, "the allocation-free solve takes FDE_P_TAU, FDE_P_TAU_HAT or FDE_P_TILDE");
+  const int n = p->n[0];
+  if (n + 1 < 8 || n + 1 > 4096)
+    return fail(FDE_EUNSUPPORTED, "the allocation-free solve needs 8 <= n + 1 <= 4096 (got n = %d)", n);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+
+  // host description of the plan (no device buffers of its own)
+  fde_plan_s pl;
+  pl.p = *p;
+  pl.dim = 1;
+  pl.n1 = n;
+  pl.n2 = 1;
+  pl.N = n;
+  pl.ld = ((long)n + 63) / 64 * 64;
+  pl.hx = (p->hi[0] - p->lo[0]) / (n + 1);
+  pl.hxa = std::pow(pl.hx, p->alpha[0]);
+  pl.nu = (p->time == FDE_T_EULER ? 1.0 : 2.0) * pl.hxa / p->dt;
+  pl.dside = p->dside;
+  pl.m = p->restart;
+  pl.rows.n = n;
+  pl.rows.P = n + 1;
+  pl.rows.logP = ilog2(pl.rows.P);
+  pl.rows.nlines = 1;
+  pl.rows.ls = n;
+  pl.rows.es = 1;
+  choose_tile(pl.rows);
+  if (!pcg_one_workgroup(&pl)) return fail(FDE_EUNSUPPORTED, "this size does not run as one workgroup");
+  const NoallocLayout L = noalloc_layout(n, pl.ld);
+  if (L.total > NOALLOC_SCRATCH_BYTES)
+    return fail(FDE_EUNSUPPORTED, "n = %d needs %zu bytes of scratch, more than the static %zu", n, L.total,
+                NOALLOC_SCRATCH_BYTES);
+  unsigned char* base = nullptr;
+  TRY(scratch_address(&base));
+  pl.stats_buf = reinterpret_cast<double*>(base + L.stats);
+
+  // coefficients: validated where the caller keeps them, read there by the kernel
+  double stats[2][3];
+  const double* src[2] = {dplus, dminus};
+  for (int i = 0; i < 2; ++i) {
+    TRY(coef_stats(&pl, src[i], stats[i], st));
+    if (stats[i][2] != 0.0) return fail(FDE_EINVAL, "coefficient array %d has a non-finite value", i);
+    if (stats[i][0] < 0.0) return fail(FDE_EINVAL, "coefficient array %d has a negative value", i);
+  }
+  pl.c64.dp = const_cast<double*>(dplus);   // read only
+  pl.c64.dm = const_cast<double*>(dminus);
+  const bool constant = stats[0][0] == stats[0][1] && stats[1][0] == stats[0][0] && stats[1][1] == stats[0][0];
+  const double cval = stats[0][0];
+  pl.has_dinv = p->prec == FDE_P_TAU;
+  if (pl.has_dinv) {
+    pl.c64.dinv = reinterpret_cast<double*>(base + L.dinv);
+    hipLaunchKernelGGL((dinv_kernel<false>), dim3(256), dim3(256), 0, st, dplus, dminus, (const double*)nullptr,
+                       (const double*)nullptr, pl.c64.dinv, reinterpret_cast<float*>(base + L.dinvf), (long)n);
+    HIPCHK(hipGetLastError());
+    double ds[3];
+    TRY(coef_stats(&pl, pl.c64.dinv, ds, st));
+    if (ds[2] != 0.0 || !(ds[0] > 0.0))
+      return fail(FDE_EINVAL, "D = mean of the coefficients has a zero (d+ and d- share a zero)");
+  }
+  // symbol samples (as fde_assemble)
+  std::vector<double> fx(n), fz(1, 0.0);
+  for (int i = 0; i < n; ++i) fx[i] = symbol(p->alpha[0], M_PI * (i + 1) / (double)(n + 1), p->weights);
+  if (p->prec == FDE_P_TAU) {
+    const double shift = std::isnan(p->shift) ? (constant ? pl.nu / cval : 0.0) : p->shift;
+    for (int i = 0; i < n; ++i) fx[i] += shift;
+  } else if (p->prec == FDE_P_TAU_HAT) {
+    if (!constant || !(cval > 0.0)) return fail(FDE_EINVAL, "P_hat needs constant, equal, positive d+ and d-");
+    for (int i = 0; i < n; ++i) fx[i] = cval * fx[i];
+    for (int i = 0; i < n; ++i) fx[i] += pl.nu;
+  } else {
+    std::vector<double> hp(n), hm(n);
+    HIPCHK(hipMemcpyAsync(hp.data(), dplus, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hm.data(), dminus, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int i = 0; i < n; ++i) {
+      fx[i] *= 0.5 * (hp[i] + hm[i]);
+      if (!(fx[i] > 0.0)) return fail(FDE_EINVAL, "P_tilde: D_j p(theta_j) must be positive");
+    }
+  }
+  std::vector<std::complex<double>> W2, lam;
+  direction_host(p->alpha[0], n, p->weights, W2, lam);
+  pl.c64.fx = reinterpret_cast<double*>(base + L.fx);
+  pl.c64.fzero = reinterpret_cast<double*>(base + L.fzero);
+  pl.c64.W2x = reinterpret_cast<cx<double>*>(base + L.W2);
+  pl.c64.lamx = reinterpret_cast<cx<double>*>(base + L.lam);
+  // std::complex<double> and cx<double> are both two adjacent doubles (real, imaginary)
+  static_assert(sizeof(std::complex<double>) == sizeof(cx<double>), "complex layouts differ");
+  HIPCHK(hipMemcpyAsync(pl.c64.fx, fx.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(pl.c64.fzero, fz.data(), sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(pl.c64.W2x, W2.data(), W2.size() * sizeof(cx<double>), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(pl.c64.lamx, lam.data(), lam.size() * sizeof(cx<double>), hipMemcpyHostToDevice, st));
+  pl.V = reinterpret_cast<double*>(base + L.vec);   // r, p, q
+  pl.Z = pl.V + 3 * pl.ld;                          // z
+  pl.ks = reinterpret_cast<KState*>(base + L.ks);
+  KState hk{};
+  pl.hks = &hk;   // the header is read back into host memory of this call
+  const fde_status s = solve_pcg_one_workgroup(&pl, b, x, info, st);   // synchronises st
+  pl.hks = nullptr;
   if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return s;
 }

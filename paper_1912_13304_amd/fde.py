@@ -35,7 +35,7 @@ EXPORTED = ["fde_default_params", "fde_assemble", "fde_matvec", "fde_tau_apply",
             "fde_plan_bytes", "fde_destroy", "fde_release_cache", "fde_last_error", "fde_probe", "fde_probe_read",
             "fde_batch_layout", "fde_batch_bytes", "fde_batch_assemble", "fde_batch_solve", "fde_batch_run",
             "fde_batch_tune", "fde_batch_get_cfg", "fde_batch_set_cfg", "fde_batch_destroy",
-            "fde_batch_matvec", "fde_batch_tau_apply"]
+            "fde_batch_matvec", "fde_batch_tau_apply", "fde_pcg1d_solve_noalloc"]
 BATCH_VARIANTS = 4
 
 
@@ -147,6 +147,8 @@ def load(path: str = LIB_PATH):
     lib.fde_batch_tau_apply.restype = ctypes.c_int
     lib.fde_batch_destroy.argtypes = [vp]
     lib.fde_batch_destroy.restype = None
+    lib.fde_pcg1d_solve_noalloc.argtypes = [dp, vp, vp, vp, vp, ctypes.POINTER(FdeInfo), vp]
+    lib.fde_pcg1d_solve_noalloc.restype = ctypes.c_int
     lib.fde_last_error.argtypes = []
     lib.fde_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -228,6 +230,15 @@ def fde_tau_apply(plan, v, z, stream=None):
 def fde_solve(plan, b, x, stream=None, allow_notconv=False) -> FdeInfo:
     info = FdeInfo()
     st = load().fde_solve(plan, _ptr(b), _ptr(x), ctypes.byref(info), _stream(stream))
+    _check(st, allow_notconv)
+    return info
+
+
+def fde_pcg1d_solve_noalloc(params: FdeParams, dplus, dminus, b, x, stream=None, allow_notconv=False) -> FdeInfo:
+    """The allocation-free one-shot 1D PCG solve (no plan)."""
+    info = FdeInfo()
+    st = load().fde_pcg1d_solve_noalloc(ctypes.byref(params), _ptr(dplus), _ptr(dminus), _ptr(b), _ptr(x),
+                                        ctypes.byref(info), _stream(stream))
     _check(st, allow_notconv)
     return info
 

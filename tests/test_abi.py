@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def header_symbols():
     txt = open(os.path.join(ROOT, "include", "fde.h")).read()
-    return sorted(set(re.findall(r"\b(fde_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(fde_[a-z0-9_]+)\s*\(", txt)))
 
 
 @pytest.fixture(scope="module")
