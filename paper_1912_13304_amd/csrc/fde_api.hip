@@ -15,6 +15,7 @@
 #include <complex>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -23,6 +24,7 @@
 
 #include "../../include/fde.h"
 #include "fde_bigline.hpp"
+#include "fde_dense.hpp"
 #include "fde_host.hpp"
 #include "fde_krylov.hpp"
 #include "fde_lines.hpp"
@@ -39,6 +41,8 @@ extern "C" const char* fde_last_error(void) { return fde::g_err.c_str(); }
 // ---------------------------------------------------------------------------
 // Plan
 // ---------------------------------------------------------------------------
+constexpr int DENSE_NMAX = 512;   // largest n per direction of the dense 2D form
+
 struct Dir {
   int n = 0, P = 0, logP = 0, nlines = 0, B = 1, logB = 0;
   long ls = 0, es = 0;
@@ -54,6 +58,7 @@ struct Consts {
   T* dinv = nullptr;                                             // D^{-1} (null: no D factor)
   T *fx = nullptr, *fy = nullptr, *fzero = nullptr;              // symbol samples
   cx<T> *W2x = nullptr, *W2y = nullptr, *lamx = nullptr, *lamy = nullptr;
+  T *stabx = nullptr, *staby = nullptr, *gx = nullptr, *gy = nullptr;  // dense 2D: sine tables, weights
 };
 
 struct fde_plan_s {
@@ -70,6 +75,7 @@ struct fde_plan_s {
   Dir ycols;         // lines along y read in place (columns of the (n2, n1) array)
   bool use_cols = false;   // y-direction passes on ycols (no transposes)
   bool big = false;  // 1D line longer than one workgroup: four-step FFT over kernels
+  bool dense = false;  // 2D: line operators as dense MFMA products (fde_dense.hpp)
   int P1 = 0, P2 = 0, log1 = 0, log2 = 0;
   Consts<double> c64;
   Consts<float> c32;
@@ -150,8 +156,11 @@ static fde_status validate(const fde_params* p) {
     if (!(p->hi[i] > p->lo[i]) || !std::isfinite(p->hi[i]) || !std::isfinite(p->lo[i]))
       return fail(FDE_EINVAL, "domain [%g, %g] is empty", p->lo[i], p->hi[i]);
     const long lim = p->dim == 1 ? (1L << 22) : 4096;
-    if (!is_pow2((long)p->n[i] + 1) || p->n[i] + 1 > lim)
-      return fail(FDE_EUNSUPPORTED, "n[%d] + 1 = %d must be a power of two <= %ld", i, p->n[i] + 1, lim);
+    const bool dense_ok = p->dim == 2 && p->n[0] <= DENSE_NMAX && p->n[1] <= DENSE_NMAX;
+    if ((!is_pow2((long)p->n[i] + 1) && !dense_ok) || p->n[i] + 1 > lim)
+      return fail(FDE_EUNSUPPORTED,
+                  "n[%d] + 1 = %d must be a power of two <= %ld (2D grids with both n <= %d take any n)", i,
+                  p->n[i] + 1, lim, DENSE_NMAX);
   }
   if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(FDE_EINVAL, "dt must be > 0 (got %g)", p->dt);
   if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return fail(FDE_EINVAL, "tol must be > 0 (got %g)", p->tol);
@@ -171,6 +180,17 @@ static fde_status validate(const fde_params* p) {
     return fail(FDE_EINVAL, "the mixed form wraps an FGMRES outer loop");
   if (!std::isnan(p->shift) && !std::isfinite(p->shift)) return fail(FDE_EINVAL, "shift must be finite or NaN");
   return FDE_OK;
+}
+
+// 2D plans whose n_1 + 1 or n_2 + 1 is not a power of two run their line
+// operators as dense products (both n <= DENSE_NMAX); FDE_DENSE_LINES=1 in
+// the environment selects that form for every 2D plan within the limit (to
+// compare the two forms).
+static bool use_dense(const fde_params* p) {
+  if (p->dim != 2 || p->n[0] > DENSE_NMAX || p->n[1] > DENSE_NMAX) return false;
+  if (!is_pow2((long)p->n[0] + 1) || !is_pow2((long)p->n[1] + 1)) return true;
+  const char* e = std::getenv("FDE_DENSE_LINES");
+  return e && e[0] == '1';
 }
 
 // Device bytes of a plan (buffers only; the kernels need no other memory).
@@ -398,6 +418,8 @@ static fde_status assemble_impl(const fde_params* p, const double* dp, const dou
     // with one column per tile every global access would be a lone element:
     // such sizes keep the transposes
     pl->use_cols = pl->ycols.B >= 2;
+    pl->dense = use_dense(p);
+    if (pl->dense) pl->use_cols = true;   // no transposed coefficient copies
   }
 
   // coefficients: validate and copy
@@ -518,7 +540,26 @@ static fde_status assemble_impl(const fde_params* p, const double* dp, const dou
   TRY(upload(pl, &pl->c32.fy, fy));
   TRY(upload(pl, &pl->c64.fzero, fz));
   TRY(upload(pl, &pl->c32.fzero, fz));
-  TRY(direction_tables(pl, p->alpha[0], n1, &pl->c64.W2x, &pl->c32.W2x, &pl->c64.lamx, &pl->c32.lamx));
+  if (pl->dense) {
+    // sine tables sqrt(2/P) sin(pi m/P), m < 2P, and the weights g_0..g_n, per direction
+    auto dense_tables = [&](double alpha, int n, double** s64, float** s32, double** g64, float** g32) -> fde_status {
+      const int P = n + 1;
+      std::vector<double> st(2 * P);
+      const double c = std::sqrt(2.0 / (double)P);
+      for (int m = 0; m < 2 * P; ++m) st[m] = c * std::sin(M_PI * (double)m / (double)P);
+      st[0] = st[P] = 0.0;
+      const std::vector<double> g = weights(alpha, n, p->weights);
+      TRY(upload(pl, s64, st));
+      TRY(upload(pl, s32, st));
+      TRY(upload(pl, g64, g));
+      TRY(upload(pl, g32, g));
+      return FDE_OK;
+    };
+    TRY(dense_tables(p->alpha[0], n1, &pl->c64.stabx, &pl->c32.stabx, &pl->c64.gx, &pl->c32.gx));
+    TRY(dense_tables(p->alpha[1], n2, &pl->c64.staby, &pl->c32.staby, &pl->c64.gy, &pl->c32.gy));
+  } else {
+    TRY(direction_tables(pl, p->alpha[0], n1, &pl->c64.W2x, &pl->c32.W2x, &pl->c64.lamx, &pl->c32.lamx));
+  }
   if (p->dim == 1 && pl->rows.P > 4096) {
     pl->big = true;
     const int L = pl->rows.logP;
@@ -539,7 +580,7 @@ static fde_status assemble_impl(const fde_params* p, const double* dp, const dou
     TRY(dalloc(pl, &pl->c64.cw, 6 * (size_t)pl->rows.P));
     if (p->precision == FDE_MIXED) TRY(dalloc(pl, &pl->c32.cw, 6 * (size_t)pl->rows.P));
   }
-  if (p->dim == 2)
+  if (p->dim == 2 && !pl->dense)
     TRY(direction_tables(pl, p->alpha[1], n2, &pl->c64.W2y, &pl->c32.W2y, &pl->c64.lamy, &pl->c32.lamy));
 
   // workspace
@@ -939,9 +980,98 @@ template <typename T>
 static void matvec_only(fde_plan pl, const T* x, T* y, T bscale, T tscale, hipStream_t st, const int* skip,
                         const int* skip2 = nullptr);
 
+// ---------------------------------------------------------------------------
+// Dense 2D form (fde_dense.hpp)
+// ---------------------------------------------------------------------------
+template <typename T, int MODE>
+static void dense_launch(fde_plan pl, DenseArgs<T> a, hipStream_t st, const int* skip, const int* skip2) {
+  a.n1 = pl->n1;
+  a.n2 = pl->n2;
+  a.skip = skip;
+  a.skip2 = skip2;
+  const dim3 grid((pl->n1 + 31) / 32, (pl->n2 + 31) / 32);
+  constexpr bool TOEP = MODE == DM_ROW_TOEP || MODE == DM_COL_TOEP;
+  const double bytes = (double)pl->N * sizeof(T) *
+                       ((a.pre != nullptr) + (a.post != nullptr) + (TOEP ? 3 + (a.base != nullptr) : 0) + 2);
+  ProbeScope ps(g_probe_plan, sizeof(T) == 8 ? FDE_PROBE_LINE64 : FDE_PROBE_LINE32, st, bytes);
+  hipLaunchKernelGGL((dense_kernel<T, MODE>), grid, dim3(256), 0, st, a);
+}
+
+// z = P^{-1}(sc * v): rows DST (D^{-1} first for D tau), columns DST, / F,
+// columns DST, rows DST (D^{-1} after for tau D).
+template <typename T>
+static void dense_tau(fde_plan pl, const T* v, const double* sc, const T* pre, const T* post, T* z, hipStream_t st,
+                      const int* skip, const int* skip2) {
+  const Consts<T>& c = consts<T>(pl);
+  T* t1 = pl->tmp<T>(1);
+  T* t2 = pl->tmp<T>(2);
+  DenseArgs<T> a{};
+  a.in = v;
+  a.sc = sc;
+  a.pre = pre;
+  a.stab = c.stabx;
+  a.out = t1;
+  dense_launch<T, DM_ROW_DST>(pl, a, st, skip, skip2);
+  DenseArgs<T> b{};
+  b.in = t1;
+  b.stab = c.staby;
+  b.fx = c.fx;
+  b.fy = c.fy;
+  b.out = t2;
+  dense_launch<T, DM_COL_DST>(pl, b, st, skip, skip2);
+  b.in = t2;
+  b.fx = b.fy = nullptr;
+  b.out = t1;
+  dense_launch<T, DM_COL_DST>(pl, b, st, skip, skip2);
+  DenseArgs<T> r{};
+  r.in = t1;
+  r.stab = c.stabx;
+  r.post = post;
+  r.out = z;
+  dense_launch<T, DM_ROW_DST>(pl, r, st, skip, skip2);
+}
+
+// y = bscale x + tscale (A_x x + kappa A_y x)
+template <typename T>
+static void dense_toep(fde_plan pl, const T* x, T* y, T bscale, T tscale, hipStream_t st, const int* skip,
+                       const int* skip2) {
+  const Consts<T>& c = consts<T>(pl);
+  T* t3 = pl->tmp<T>(3);
+  DenseArgs<T> a{};
+  a.in = x;
+  a.g = c.gx;
+  a.cp = c.dp;
+  a.cm = c.dm;
+  a.bscale = bscale;
+  a.tscale = tscale;
+  a.out = t3;
+  dense_launch<T, DM_ROW_TOEP>(pl, a, st, skip, skip2);
+  DenseArgs<T> b{};
+  b.in = x;
+  b.g = c.gy;
+  b.cp = c.ep;
+  b.cm = c.em;
+  b.base = t3;
+  b.bscale = T(1);
+  b.tscale = tscale * (T)pl->kappa;
+  b.out = y;
+  dense_launch<T, DM_COL_TOEP>(pl, b, st, skip, skip2);
+}
+
 template <typename T>
 static void tau_matvec(fde_plan pl, const T* v, const double* sc, T* z, T* w, hipStream_t st, const int* skip,
                        const int* skip2) {
+  if (pl->dense) {   // 2D callers always pass z
+    const Consts<T>& c = consts<T>(pl);
+    if (pl->p.prec == FDE_P_NONE)
+      hipLaunchKernelGGL((scale_cast_kernel<T, T>), dim3(ew_grid(pl->N)), dim3(256), 0, st, v, z, pl->N, sc, skip,
+                         skip2);
+    else
+      dense_tau<T>(pl, v, sc, (pl->has_dinv && pl->dside == FDE_D_LEFT) ? c.dinv : nullptr,
+                   (pl->has_dinv && pl->dside == FDE_D_RIGHT) ? c.dinv : nullptr, z, st, skip, skip2);
+    dense_toep<T>(pl, z, w, (T)pl->nu, T(1), st, skip, skip2);
+    return;
+  }
   if (pl->p.prec == FDE_P_TRI) {
     tri_apply<T>(pl, v, sc, z, st, skip, skip2);
     matvec_only<T>(pl, z, w, (T)pl->nu, T(1), st, skip, skip2);
@@ -1042,6 +1172,10 @@ static void tau_only(fde_plan pl, const T* v, const double* sc, T* z, hipStream_
     big_tau<T>(pl, v, sc, pre, post, z, nullptr, st, skip, skip2);
     return;
   }
+  if (pl->dense) {
+    dense_tau<T>(pl, v, sc, pre, post, z, st, skip, skip2);
+    return;
+  }
   if (pl->dim == 1) {
     LineArgs<T> a{};
     a.in = v;
@@ -1085,6 +1219,10 @@ static void matvec_only(fde_plan pl, const T* x, T* y, T bscale, T tscale, hipSt
                         const int* skip2) {
   if (pl->dim == 1 && pl->big) {
     big_toep<T>(pl, x, x, bscale, tscale, y, st, skip, skip2);
+    return;
+  }
+  if (pl->dense) {
+    dense_toep<T>(pl, x, y, bscale, tscale, st, skip, skip2);
     return;
   }
   LineArgs<T> a = toep_args<T>(pl, false, skip, skip2);
