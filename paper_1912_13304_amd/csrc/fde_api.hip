@@ -41,7 +41,15 @@ extern "C" const char* fde_last_error(void) { return fde::g_err.c_str(); }
 // ---------------------------------------------------------------------------
 // Plan
 // ---------------------------------------------------------------------------
-constexpr int DENSE_NMAX = 512;   // largest n per direction of the dense 2D form
+constexpr int DENSE_NMAX = 512;       // largest n per direction of the dense 2D form
+constexpr int CHIRP_NMAX = 1 << 21;   // largest 1D n whose n + 1 need not be a power of two
+constexpr int FOURSTEP_MIN = 4096;    // smallest four-step FFT length (both factors >= 64)
+
+// FFT lengths of a 1D line on the four-step path: the Toeplitz embedding's
+// (a power of two >= n + 1, = n + 1 when that is one) and, for the chirp-z
+// DST, the convolution's (a power of two >= 2n - 1); both at least FOURSTEP_MIN.
+static long toep_len(long n) { return std::max<long>(FOURSTEP_MIN, 1L << ilog2(n + 1)); }
+static long chirp_len(long n) { return std::max<long>(FOURSTEP_MIN, 1L << ilog2(std::max(2 * n - 1, 1L))); }
 
 struct Dir {
   int n = 0, P = 0, logP = 0, nlines = 0, B = 1, logB = 0;
@@ -52,7 +60,11 @@ struct Dir {
 template <typename T>
 struct Consts {
   cx<T> *W2p1 = nullptr, *W2p2 = nullptr;                        // four-step factor twiddles (big lines)
-  cx<T>* cw = nullptr;                                           // big-line complex work, 6P
+  cx<T>* cw = nullptr;                                           // big-line complex work, 6 max(P, Q)
+  // chirp-z DST of a 1D line whose n + 1 is not a power of two: four-step
+  // factor twiddles and exp(-i pi m/Q) of the length-Q FFTs, chirp c_j
+  // (j <= n) and the chirp filter's spectrum (Q entries)
+  cx<T> *Ws1 = nullptr, *Ws2 = nullptr, *Wsb = nullptr, *chirp = nullptr, *bhat = nullptr;
   T *dp = nullptr, *dm = nullptr, *ep = nullptr, *em = nullptr;  // coefficients
   T *ept = nullptr, *emt = nullptr;                              // e+- transposed (n1 x n2)
   T* dinv = nullptr;                                             // D^{-1} (null: no D factor)
@@ -76,7 +88,11 @@ struct fde_plan_s {
   bool use_cols = false;   // y-direction passes on ycols (no transposes)
   bool big = false;  // 1D line longer than one workgroup: four-step FFT over kernels
   bool dense = false;  // 2D: line operators as dense MFMA products (fde_dense.hpp)
-  int P1 = 0, P2 = 0, log1 = 0, log2 = 0;
+  int P1 = 0, P2 = 0, log1 = 0, log2 = 0;   // four-step factors of the Toeplitz FFT length rows.P
+  bool blue = false;  // 1D, n + 1 not a power of two: rows.P >= n + 1 pads the Toeplitz embedding and
+                      // the DST takes the chirp-z form with FFTs of length sQ
+  long sQ = 0;
+  int sQ1 = 0, sQ2 = 0, slog1 = 0, slog2 = 0;
   Consts<double> c64;
   Consts<float> c32;
   int m = 30, kin = 0;
@@ -157,10 +173,11 @@ static fde_status validate(const fde_params* p) {
       return fail(FDE_EINVAL, "domain [%g, %g] is empty", p->lo[i], p->hi[i]);
     const long lim = p->dim == 1 ? (1L << 22) : 4096;
     const bool dense_ok = p->dim == 2 && p->n[0] <= DENSE_NMAX && p->n[1] <= DENSE_NMAX;
-    if ((!is_pow2((long)p->n[i] + 1) && !dense_ok) || p->n[i] + 1 > lim)
+    const bool chirp_ok = p->dim == 1 && p->n[0] <= CHIRP_NMAX;
+    if ((!is_pow2((long)p->n[i] + 1) && !dense_ok && !chirp_ok) || p->n[i] + 1 > lim)
       return fail(FDE_EUNSUPPORTED,
-                  "n[%d] + 1 = %d must be a power of two <= %ld (2D grids with both n <= %d take any n)", i,
-                  p->n[i] + 1, lim, DENSE_NMAX);
+                  "n[%d] + 1 = %d must be a power of two <= %ld (1D lines with n <= %d and 2D grids with both "
+                  "n <= %d take any n)", i, p->n[i] + 1, lim, CHIRP_NMAX, DENSE_NMAX);
   }
   if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(FDE_EINVAL, "dt must be > 0 (got %g)", p->dt);
   if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return fail(FDE_EINVAL, "tol must be > 0 (got %g)", p->tol);
@@ -208,7 +225,12 @@ static size_t plan_bytes_impl(const fde_params* p) {
   else b += (size_t)((N + 63) / 64 * 64) * 8 * (2 * m + 1) + (size_t)N * 8 * 3;
   if (p->precision == FDE_MIXED) b += (size_t)((N + 63) / 64 * 64) * 4 * (p->inner_steps + 1) + (size_t)N * 4 * 6;
   b += (size_t)RED_MAXG * (KMAX + 1) * 8 + 2 * sizeof(KState);
-  if (p->dim == 1 && n1 + 1 > 4096) b += (size_t)(n1 + 1) * (6 * 16 + (p->precision == FDE_MIXED ? 6 * 8 : 0) + 8 * 24);
+  if (p->dim == 1 && !is_pow2(n1 + 1)) {
+    const size_t L = (size_t)std::max(toep_len(n1), chirp_len(n1));
+    b += L * (6 * 16 + (p->precision == FDE_MIXED ? 6 * 8 : 0) + 8 * 24) + (size_t)(n1 + 1 + chirp_len(n1)) * 24;
+  } else if (p->dim == 1 && n1 + 1 > 4096) {
+    b += (size_t)(n1 + 1) * (6 * 16 + (p->precision == FDE_MIXED ? 6 * 8 : 0) + 8 * 24);
+  }
   if (p->prec == FDE_P_TRI) b += (size_t)N * 6 * (8 + 4) + (size_t)TRI_PMAX * (7 * (8 + 4) + 4) + 4;
   return b;
 }
@@ -255,8 +277,8 @@ static fde_status upload_cx(fde_plan pl, cx<T>** dst, const std::vector<std::com
 // 2P x 2P circulant whose leading n x n block is T (or S): first column
 // (-g_1, ..., -g_n, 0, ..., 0, -g_0).
 static void direction_host(double alpha, int n, int kind, std::vector<std::complex<double>>& W2,
-                           std::vector<std::complex<double>>& lam) {
-  const int P = n + 1;
+                           std::vector<std::complex<double>>& lam, long Pt = 0) {
+  const long P = Pt ? Pt : n + 1;   // FFT length; the circulant of length 2P embeds T when P >= n + 1
   W2.assign(2 * P, 0.0);
   lam.assign(2 * P, 0.0);
   for (int m = 0; m < 2 * P; ++m) {
@@ -265,7 +287,7 @@ static void direction_host(double alpha, int n, int kind, std::vector<std::compl
     W2[m] = std::complex<double>(std::cos(M_PI * t), -std::sin(M_PI * t));
   }
   // exact values at multiples of pi/2
-  for (int m = 0; m < 2 * P; m += std::max(1, P / 2)) {
+  for (long m = 0; m < 2 * P; m += std::max(1L, P / 2)) {
     const int q = (int)((2L * m) / P) & 3;
     if ((2L * m) % P == 0) W2[m] = q == 0 ? 1.0 : q == 1 ? std::complex<double>(0, -1) : q == 2 ? -1.0 : std::complex<double>(0, 1);
   }
@@ -277,9 +299,9 @@ static void direction_host(double alpha, int n, int kind, std::vector<std::compl
 }
 
 static fde_status direction_tables(fde_plan pl, double alpha, int n, cx<double>** W2d, cx<float>** W2f,
-                                   cx<double>** lamd, cx<float>** lamf) {
+                                   cx<double>** lamd, cx<float>** lamf, long Pt = 0) {
   std::vector<std::complex<double>> W2, lam;
-  direction_host(alpha, n, pl->p.weights, W2, lam);
+  direction_host(alpha, n, pl->p.weights, W2, lam, Pt);
   TRY(upload_cx(pl, W2d, W2));
   TRY(upload_cx(pl, W2f, W2));
   TRY(upload_cx(pl, lamd, lam));
@@ -540,6 +562,14 @@ static fde_status assemble_impl(const fde_params* p, const double* dp, const dou
   TRY(upload(pl, &pl->c32.fy, fy));
   TRY(upload(pl, &pl->c64.fzero, fz));
   TRY(upload(pl, &pl->c32.fzero, fz));
+  if (p->dim == 1 && (pl->n1 + 1 > 4096 || !is_pow2(pl->n1 + 1))) {
+    // the four-step path: Toeplitz FFT length rows.P (n + 1, or a padded
+    // power of two for the chirp-z form)
+    pl->big = true;
+    pl->blue = !is_pow2(pl->n1 + 1);
+    pl->rows.P = (int)toep_len(pl->n1);
+    pl->rows.logP = ilog2(pl->rows.P);
+  }
   if (pl->dense) {
     // sine tables sqrt(2/P) sin(pi m/P), m < 2P, and the weights g_0..g_n, per direction
     auto dense_tables = [&](double alpha, int n, double** s64, float** s32, double** g64, float** g32) -> fde_status {
@@ -558,10 +588,10 @@ static fde_status assemble_impl(const fde_params* p, const double* dp, const dou
     TRY(dense_tables(p->alpha[0], n1, &pl->c64.stabx, &pl->c32.stabx, &pl->c64.gx, &pl->c32.gx));
     TRY(dense_tables(p->alpha[1], n2, &pl->c64.staby, &pl->c32.staby, &pl->c64.gy, &pl->c32.gy));
   } else {
-    TRY(direction_tables(pl, p->alpha[0], n1, &pl->c64.W2x, &pl->c32.W2x, &pl->c64.lamx, &pl->c32.lamx));
+    TRY(direction_tables(pl, p->alpha[0], n1, &pl->c64.W2x, &pl->c32.W2x, &pl->c64.lamx, &pl->c32.lamx,
+                         pl->rows.P));
   }
-  if (p->dim == 1 && pl->rows.P > 4096) {
-    pl->big = true;
+  if (pl->big) {
     const int L = pl->rows.logP;
     pl->log1 = (L + 1) / 2;
     pl->log2 = L / 2;
@@ -577,8 +607,43 @@ static fde_status assemble_impl(const fde_params* p, const double* dp, const dou
     };
     TRY(sub(pl->P1, &pl->c64.W2p1, &pl->c32.W2p1));
     TRY(sub(pl->P2, &pl->c64.W2p2, &pl->c32.W2p2));
-    TRY(dalloc(pl, &pl->c64.cw, 6 * (size_t)pl->rows.P));
-    if (p->precision == FDE_MIXED) TRY(dalloc(pl, &pl->c32.cw, 6 * (size_t)pl->rows.P));
+    long work = pl->rows.P;
+    if (pl->blue) {
+      // chirp-z DST: FFT length sQ >= 2n - 1, its four-step factors, the chirp
+      // c_j = exp(i pi j^2/(2P)) (j <= n, P = n + 1; j^2 reduced mod 4P) and the
+      // spectrum of the filter conj(c_m), |m| < n, times sqrt(2/P)/sQ
+      pl->sQ = chirp_len(n1);
+      const int LQ = ilog2(pl->sQ);
+      pl->slog1 = (LQ + 1) / 2;
+      pl->slog2 = LQ / 2;
+      pl->sQ1 = 1 << pl->slog1;
+      pl->sQ2 = 1 << pl->slog2;
+      TRY(sub(pl->sQ1, &pl->c64.Ws1, &pl->c32.Ws1));
+      TRY(sub(pl->sQ2, &pl->c64.Ws2, &pl->c32.Ws2));
+      TRY(sub((int)pl->sQ, &pl->c64.Wsb, &pl->c32.Wsb));
+      const long P = n1 + 1;
+      auto ph = [&](long j, double sgn) {
+        const long r = (j * j) % (4 * P);
+        const double t = M_PI * (double)r / (2.0 * (double)P);
+        return std::complex<double>(std::cos(t), sgn * std::sin(t));
+      };
+      std::vector<std::complex<double>> chirp(n1 + 1), bhat(pl->sQ, 0.0);
+      for (long j = 0; j <= n1; ++j) chirp[j] = ph(j, 1.0);
+      for (long r = 0; r < n1; ++r) {
+        bhat[r] = ph(r, -1.0);
+        if (r) bhat[pl->sQ - r] = bhat[r];
+      }
+      host_fft(bhat);
+      const double sc = std::sqrt(2.0 / (double)P) / (double)pl->sQ;
+      for (auto& v : bhat) v *= sc;
+      TRY(upload_cx(pl, &pl->c64.chirp, chirp));
+      TRY(upload_cx(pl, &pl->c32.chirp, chirp));
+      TRY(upload_cx(pl, &pl->c64.bhat, bhat));
+      TRY(upload_cx(pl, &pl->c32.bhat, bhat));
+      work = std::max(work, pl->sQ);
+    }
+    TRY(dalloc(pl, &pl->c64.cw, 6 * (size_t)work));
+    if (p->precision == FDE_MIXED) TRY(dalloc(pl, &pl->c32.cw, 6 * (size_t)work));
   }
   if (p->dim == 2 && !pl->dense)
     TRY(direction_tables(pl, p->alpha[1], n2, &pl->c64.W2y, &pl->c32.W2y, &pl->c64.lamy, &pl->c32.lamy));
@@ -890,8 +955,15 @@ static void fourstep(int lg, LD in, cx<T>* out, long P, int P1, int P2, int batc
 // `out` may be one of them.
 template <typename T, class LD>
 static void big_fft(fde_plan pl, LD ld, cx<T>* out, cx<T>* tmp, int batch, hipStream_t st, const int* skip,
-                    const int* skip2) {
+                    const int* skip2, bool chirp = false) {
   const Consts<T>& c = consts<T>(pl);
+  if (chirp) {   // the chirp-z DST's length-sQ FFT
+    const long Q = pl->sQ;
+    fourstep<T, true>(pl->slog1, ld, tmp, Q, pl->sQ1, pl->sQ2, batch, c.Ws1, c.Wsb, st, skip, skip2);
+    fourstep<T, false>(pl->slog2, LdArray<T>{tmp, Q}, out, Q, pl->sQ1, pl->sQ2, batch, c.Ws2, c.Wsb, st, skip,
+                       skip2);
+    return;
+  }
   const long P = pl->rows.P;
   fourstep<T, true>(pl->log1, ld, tmp, P, pl->P1, pl->P2, batch, c.W2p1, c.W2x, st, skip, skip2);   // columns
   fourstep<T, false>(pl->log2, LdArray<T>{tmp, P}, out, P, pl->P1, pl->P2, batch, c.W2p2, c.W2x, st, skip,
@@ -906,6 +978,18 @@ static void big_tau(fde_plan pl, const T* v, const double* sc, const T* pre, con
                     hipStream_t st, const int* skip, const int* skip2) {
   const Consts<T>& c = consts<T>(pl);
   const int P = pl->rows.P, n = pl->n1;
+  if (pl->blue) {   // chirp-z DST, divide by F, chirp-z DST
+    const long Q = pl->sQ;
+    cx<T>* a0 = c.cw;
+    cx<T>* a1 = c.cw + Q;
+    big_fft<T>(pl, LdChirpIn<T>{v, pre, sc, c.chirp, n}, a0, a1, 1, st, skip, skip2, true);
+    big_fft<T>(pl, LdChirpMul<T>{a0, c.bhat}, a0, a1, 1, st, skip, skip2, true);
+    big_fft<T>(pl, LdChirpMid<T>{a0, c.chirp, c.fx, n}, a0, a1, 1, st, skip, skip2, true);
+    big_fft<T>(pl, LdChirpMul<T>{a0, c.bhat}, a0, a1, 1, st, skip, skip2, true);
+    hipLaunchKernelGGL((unpack_chirp_kernel<T>), dim3(ew_grid(n)), dim3(256), 0, st, a0, c.chirp, post, z, z2, n,
+                       skip, skip2);
+    return;
+  }
   cx<T>* c0 = c.cw;
   cx<T>* c1 = c.cw + P;
   const int g = ew_grid(P);

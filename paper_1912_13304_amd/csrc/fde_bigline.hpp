@@ -222,6 +222,76 @@ struct LdPairToep {
   }
 };
 
+// ---------------------------------------------------------------------------
+// DST-I of a line whose n + 1 is not a power of two (chirp-z form).  With
+// P = n + 1 and c_j = exp(i pi j^2 / (2P)), jk = (j^2 + k^2 - (k-j)^2)/2 turns
+// sum_j x_j sin(pi jk/P) into Im(c_k sum_j (x_j c_j) conj(c_{k-j})): a
+// convolution with the chirp, done with power-of-two FFTs of length Q >= 2n - 1
+// (the chirp filter's spectrum bhat is precomputed, with the factor
+// sqrt(2/P)/Q).  Index j of the FFT input holds entry j + 1 of the line.
+// ---------------------------------------------------------------------------
+
+// First FFT input: a_j = sc pre_j in_j c_{j+1} (j < n), zero beyond.
+template <typename T>
+struct LdChirpIn {
+  const T* in;
+  const T* pre;
+  const double* sc;
+  const cx<T>* chirp;
+  int n;
+  __device__ cx<T> operator()(long, long j) const {
+    if (j >= n) return mk(T(0), T(0));
+    T u = in[j];
+    if (sc) u *= (T)(*sc);
+    if (pre) u *= pre[j];
+    const cx<T> c = chirp[j + 1];
+    return mk(u * c.x, u * c.y);
+  }
+};
+
+// Second FFT input: conj(A_k bhat_k) (an inverse FFT as a forward one).
+template <typename T>
+struct LdChirpMul {
+  const cx<T>* A;
+  const cx<T>* bhat;
+  __device__ cx<T> operator()(long, long k) const { return conj(mul(A[k], bhat[k])); }
+};
+
+// DST value y_{k+1} = Im(c_{k+1} conj(R_k)) from the second FFT's output R.
+template <typename T>
+__device__ __forceinline__ T chirp_value(const cx<T>* R, const cx<T>* chirp, long k) {
+  const cx<T> r = R[k], c = chirp[k + 1];
+  return c.y * r.x - c.x * r.y;
+}
+
+// Between the two DSTs of the preconditioner: y / F, chirped for the next DST.
+template <typename T>
+struct LdChirpMid {
+  const cx<T>* R;
+  const cx<T>* chirp;
+  const T* f;
+  int n;
+  __device__ cx<T> operator()(long, long j) const {
+    if (j >= n) return mk(T(0), T(0));
+    const T u = chirp_value(R, chirp, j) / f[j];
+    const cx<T> c = chirp[j + 1];
+    return mk(u * c.x, u * c.y);
+  }
+};
+
+// out[m] = post_m y_{m+1}, m < n (and a second copy when out2).
+template <typename T>
+__global__ void unpack_chirp_kernel(const cx<T>* R, const cx<T>* chirp, const T* post, T* out, T* out2, int n,
+                                    const int* skip, const int* skip2) {
+  if (skip2f(skip, skip2)) return;
+  for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < n; m += gridDim.x * blockDim.x) {
+    T y = chirp_value(R, chirp, m);
+    if (post) y *= post[m];
+    out[m] = y;
+    if (out2) out2[m] = y;
+  }
+}
+
 // out_m = bscale * base_m + tscale * (cplus_m y1_m + cminus_m y2_m), where
 // y_{2j} = Re R_j / P and y_{2j+1} = -Im R_j / P for R = FFT(conj W).
 template <typename T>

@@ -49,7 +49,7 @@ def test_defaults(fde):
 @pytest.mark.parametrize("field,value,status", [
     ("dim", 3, -1), ("alpha", (1.0, 1.5), -1), ("alpha", (2.0, 1.5), -1), ("dt", 0.0, -1),
     ("tol", -1.0, -1), ("restart", 0, -1), ("restart", 33, -1), ("maxit", 0, -1),
-    ("n", (1000, 1), -5), ("n", (0, 1), -1), ("prec", 9, -1), ("solver", 5, -1),
+    ("n", (3000000, 1), -5), ("n", (0, 1), -1), ("prec", 9, -1), ("solver", 5, -1),
 ])
 def test_invalid_parameters_rejected_before_device_work(fde, field, value, status):
     p = fde.fde_default_params()
