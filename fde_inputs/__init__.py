@@ -211,11 +211,12 @@ class Arrival:
     problem: Problem
 
 
-def served_stream(rate: float, count: int, seed: int = 5, pow2: bool = True,
+def served_stream(rate: float, count: int, seed: int = 5, pow2: bool = False,
                   n1d=(1023, 65535), n2d=(127, 255, 511, 1023),
                   steps=(5, 50)) -> list:
     """Poisson arrivals of time-stepping requests: 70% 1D (n log-uniform in
-    n1d), 30% 2D with n in n2d; alpha ~ U(1.1, 1.9); 5..50 steps each."""
+    n1d, any integer; pow2=True rounds it to the nearest 2^k - 1), 30% 2D with
+    n in n2d; alpha ~ U(1.1, 1.9); 5..50 steps each."""
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []

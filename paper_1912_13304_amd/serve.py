@@ -37,6 +37,7 @@ class Result:
     inner_iters: List[int] = field(default_factory=list)
     relres: List[float] = field(default_factory=list)
     u: Optional[object] = None   # final state (device tensor) when keep_state
+    states: Optional[list] = None  # every step's state (host arrays) when keep_state == "all"
     status: int = 0              # fde status of the failed call (0: every step solved)
     error: str = ""              # its message
 
@@ -81,7 +82,9 @@ def footprint(problem, **kw) -> int:
 
 def run_job(problem, stream=None, keep_state=False, **kw):
     """One time-stepping job on the current device: assemble, then for every
-    step b = rhs(u), solve M u_new = b from u_new = u.  Returns (infos, u)."""
+    step b = rhs(u), solve M u_new = b from u_new = u.  Returns (infos, u);
+    keep_state="all" returns (infos, u, host copies of the state after every
+    step) instead (checking only: a host copy per step)."""
     import torch
     dev = torch.device("cuda", torch.cuda.current_device())
     T = lambda a: None if a is None else torch.as_tensor(a, dtype=torch.float64, device=dev).reshape(-1).contiguous()
@@ -91,15 +94,19 @@ def run_job(problem, stream=None, keep_state=False, **kw):
     b = torch.empty_like(u)
     params = fde.params_for(problem, **kw)
     handle = fde.fde_assemble(params, *coef, stream=stream)
-    infos = []
+    infos, states = [], []
     try:
         for _ in range(problem.steps):
             fde.fde_rhs(handle, u, None, b, stream=stream)
             x.copy_(u)
             infos.append(fde.fde_solve(handle, b, x, stream=stream))
             u, x = x, u
+            if keep_state == "all":
+                states.append(u.detach().cpu().numpy())
     finally:
         fde.fde_destroy(handle)
+    if keep_state == "all":
+        return infos, u, states
     return infos, (u if keep_state else None)
 
 
@@ -171,13 +178,17 @@ class Server:
             arr, prob, need = item
             start = self.now()
             try:
+                states = None
                 with torch.cuda.stream(stream):
-                    infos, u = run_job(prob, stream=stream.cuda_stream, keep_state=self.keep_state,
-                                       **request_kw(prob, self.solve_kw))
+                    out = run_job(prob, stream=stream.cuda_stream, keep_state=self.keep_state,
+                                  **request_kw(prob, self.solve_kw))
                     stream.synchronize()
+                infos, u = out[0], out[1]
+                if self.keep_state == "all":
+                    states = out[2]
                 res = Result(prob.name, arr, start, self.now(), prob.steps,
                              [i.iters for i in infos], [i.inner_iters for i in infos],
-                             [i.relres_true for i in infos], u)
+                             [i.relres_true for i in infos], u, states)
             except Exception as e:   # a failed request is reported; the slot keeps serving
                 stream.synchronize()
                 status = e.status if isinstance(e, fde.FdeError) else fde.FDE_EINVAL
@@ -203,14 +214,35 @@ def serve_stream(arrivals, slots: int = 4, hbm_budget: float = 64e9, keep_state:
     return srv.results, srv.now()
 
 
-def latency_stats(results) -> dict:
+def latency_stats(results, slots: Optional[int] = None) -> dict:
     """Latency percentiles and throughput over the completed requests; failed
-    requests are counted separately and contribute no solves."""
+    requests are counted separately and contribute no solves.  With `slots`,
+    also the utilisation: the fraction of the span during which at least one
+    request was in service, the mean number in service, and the mean wait
+    between arrival and admission."""
     import numpy as np
     done = [r for r in results if r.ok]
     lat = np.array([r.latency for r in done]) if done else np.zeros(1)
     solves = sum(r.steps for r in done)
-    span = (max(r.finish for r in results) - min(r.arrival for r in results)) if results else 0.0
-    return {"requests": len(results), "failed": len(results) - len(done), "solves": solves,
-            "p50_ms": float(1e3 * np.percentile(lat, 50)), "p99_ms": float(1e3 * np.percentile(lat, 99)),
-            "mean_ms": float(1e3 * lat.mean()), "solves_per_s": solves / span if span > 0 else 0.0}
+    t0 = min(r.arrival for r in results) if results else 0.0
+    span = (max(r.finish for r in results) - t0) if results else 0.0
+    out = {"requests": len(results), "failed": len(results) - len(done), "solves": solves,
+           "p50_ms": float(1e3 * np.percentile(lat, 50)), "p99_ms": float(1e3 * np.percentile(lat, 99)),
+           "mean_ms": float(1e3 * lat.mean()), "solves_per_s": solves / span if span > 0 else 0.0,
+           "span_s": span}
+    if slots and results and span > 0:
+        # busy time: the union of the service intervals
+        iv = sorted((r.start, r.finish) for r in results)
+        busy, cs, ce = 0.0, iv[0][0], iv[0][1]
+        for a, b in iv[1:]:
+            if a > ce:
+                busy += ce - cs
+                cs, ce = a, b
+            else:
+                ce = max(ce, b)
+        busy += ce - cs
+        service = sum(r.finish - r.start for r in results)
+        out.update(busy_fraction=busy / span, mean_in_service=service / span,
+                   slot_utilisation=service / (slots * span),
+                   mean_wait_ms=float(1e3 * np.mean([r.start - r.arrival for r in results])))
+    return out

@@ -79,3 +79,53 @@ def test_failed_request_is_reported_and_slot_survives():
     assert all(r.ok for r in results if r.name != bad.name)
     st = serve.latency_stats(results)
     assert st["failed"] == 1 and st["requests"] == len(arr)
+
+
+def test_served_results_against_oracle():
+    """Served results checked step by step against the oracle (each step
+    from the state the server computed before it): float64 requests mirror
+    the oracle's FGMRES (iterations within one, iterates at equal step count
+    within 1e-10); mixed requests have a float64 true residual within the
+    tolerance and are within Varah's bound of the oracle's step.  The stream
+    includes 1D lines whose n + 1 is not a power of two (chirp-z DST)."""
+    import numpy as np
+    from gpu_util import mirror_check, rounding_spread
+    from oracle import krylov, precond as pc
+    from oracle.system import FDESystem
+    fde = need_gpu()
+    from paper_1912_13304_amd import serve
+    arr = fi.served_stream(2000.0, 6, seed=31, n1d=(300, 3000), n2d=(31, 63), steps=(2, 3))
+    for precision in (fde.FP64, fde.MIXED):
+        results, _ = serve.serve_stream(arr, slots=3, keep_state="all", precision=precision,
+                                        inner_steps=serve.AUTO)
+        by = {r.name: r for r in results}
+        for a in arr:
+            p = a.problem
+            r = by[p.name]
+            assert r.ok and len(r.states) == p.steps
+            s = FDESystem.from_problem(p)
+            P = pc.make("tau", s)
+            prev = p.u0.reshape(-1)
+            for m, xg in enumerate(r.states):
+                xg = xg.reshape(-1)
+                b = s.rhs(prev)
+
+                def orun(maxit, b=b, prev=prev):
+                    x, i = krylov.fgmres(s.matvec, b, P, x0=prev, restart=30, tol=p.tol, maxit=maxit or 100000)
+                    return x, i["iters"]
+
+                if precision == fde.FP64:
+                    def grun(maxit, b=b, prev=prev):
+                        with fde.Plan(p, maxit=maxit) as plan:
+                            x = torch.as_tensor(prev.copy(), device="cuda")
+                            i = plan.solve(torch.as_tensor(b, device="cuda"), x, allow_notconv=True)
+                            return x.cpu().numpy(), i.iters
+                    spread = (lambda b=b, prev=prev: rounding_spread(s, b, P, prev, tol=p.tol)) \
+                        if p.dim == 1 else None
+                    mirror_check(xg, r.iters[m], orun, grun, spread=spread)
+                else:
+                    xo, _ = orun(None)
+                    rg, ro = b - s.matvec(xg), b - s.matvec(xo)
+                    assert np.linalg.norm(rg) <= p.tol * (1 + 1e-6) * np.linalg.norm(b)
+                    assert np.abs(xg - xo).max() <= (np.abs(rg).max() + np.abs(ro).max()) / s.nu
+                prev = xg
