@@ -137,7 +137,7 @@ def batched_leg(args, fi, fde, torch, np):
             c = bt.tune(u)
             cfg = c.as_dict()
         else:
-            bt.set_cfg(cfg["variant"], cfg["grid"], cfg["lpt"])
+            bt.set_cfg(cfg["variant"], cfg["grid"], cfg["lpt"], cfg.get("split", 0))
         bt.run(u.clone(), 1, use_graph=True, allow_notconv=True)   # warm (graph captured)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -177,7 +177,7 @@ def batched_leg(args, fi, fde, torch, np):
     for pl in plans:
         pl.close()
     bt = fde.Batch(sample)
-    bt.set_cfg(cfg["variant"], cfg["grid"], cfg["lpt"])
+    bt.set_cfg(cfg["variant"], cfg["grid"], cfg["lpt"], cfg.get("split", 0))
     u = bt.pack([p.u0 for p in sample])
     bt.run(u.clone(), 1, use_graph=False, allow_notconv=True)
     torch.cuda.synchronize()

@@ -201,14 +201,20 @@ typedef struct fde_batch_s* fde_batch;
    (0: 512 threads, radix 8; 1: 512 threads, radix 4; 2 and 3, the
    256-thread forms, are disabled and rejected with FDE_EUNSUPPORTED); grid
    is the number of persistent workgroups; lpt = 1 hands out instances
-   longest-estimated-work first, 0 in the given order.  ms: the time of one
-   step measured by the tuner. */
+   longest-estimated-work first, 0 in the given order; split = the number of
+   instances with the largest estimated work (iterations of their last solve
+   times n log n, or n log n before any) taken out of the persistent launch
+   and solved on the plan path (fde_assemble + fde_solve, built on first use),
+   by host worker threads on streams of their own, concurrently with the
+   launch: a large, slow instance then runs on all CUs instead of one.  ms:
+   the time of one step measured by the tuner. */
 enum { FDE_BATCH_VARIANTS = 4 };
 typedef struct {
   int    variant;
   int    grid;
   int    lpt;
   double ms;
+  int    split;
 } fde_batch_cfg;
 
 /* Offsets of the packed layout (offsets: host array of count + 1 entries, or
@@ -253,7 +259,8 @@ fde_status fde_batch_run(fde_batch batch, double* u, int steps, int use_graph, f
                          void* stream);
 
 /* Autotuner: times one time step from the packed state u (not modified) for
-   every launch configuration and keeps the fastest; `chosen` (may be NULL)
+   every launch configuration (variant x grid x order, then split counts
+   with the best of those) and keeps the fastest; `chosen` (may be NULL)
    receives it.  Synchronises `stream`. */
 fde_status fde_batch_tune(fde_batch batch, const double* u, void* stream, fde_batch_cfg* chosen);
 fde_status fde_batch_get_cfg(fde_batch batch, fde_batch_cfg* cfg);

@@ -13,6 +13,7 @@
 #include <complex>
 #include <cstring>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "../../include/fde.h"
@@ -177,7 +178,7 @@ struct fde_batch_s {
   long total = 0;
   int logTW = 0;
   Inst* dinst = nullptr;
-  int *order_lpt = nullptr, *order_nat = nullptr;
+  std::vector<int> hq;   // host copy of the queue order
   unsigned* queue = nullptr;
   int* step = nullptr;
   Info* info = nullptr;
@@ -187,15 +188,27 @@ struct fde_batch_s {
   double* tune_x = nullptr;
   std::vector<void*> allocs;
   size_t bytes = 0;
-  fde_batch_cfg cfg{0, 0, 1, 0.0};
+  fde_batch_cfg cfg{0, 0, 1, 0.0, 0};
   int cus = 256;
+  int dev = 0;
   // captured graph of one time step
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   double* gx = nullptr;
-  fde_batch_cfg gcfg{-1, -1, -1, 0.0};
+  fde_batch_cfg gcfg{-1, -1, -1, 0.0, -1};
   std::vector<Info> hinfo;
+  // instances taken out of the persistent launch (cfg.split of them, the
+  // largest estimated work) and solved on the plan path by worker threads
+  std::vector<double> cost;             // per-iteration work model of each instance
+  std::vector<int> last_iters;          // iterations of each instance's last solve (0: not known)
+  std::vector<const double*> hdp, hdm;  // the instance's coefficients in the arena
+  std::vector<double*> hb;              // the instance's right-hand-side buffer in the arena
+  std::vector<int> split_idx;           // current split set, largest estimated work first
+  std::vector<fde_plan> plans;          // per instance, built when it is first split
+  std::vector<hipStream_t> wstreams;    // worker streams
+  int* order_q = nullptr;               // queue order of the launch (count entries, nq used)
+  int nq = 0;
 };
 
 namespace {
@@ -218,13 +231,16 @@ void drop_graph(fde_batch bt) {
   bt->gexec = nullptr;
   bt->graph = nullptr;
   bt->gx = nullptr;
-  bt->gcfg = fde_batch_cfg{-1, -1, -1, 0.0};
+  bt->gcfg = fde_batch_cfg{-1, -1, -1, 0.0, -1};
 }
 
 void destroy_impl(fde_batch bt) {
   if (!bt) return;
   (void)hipDeviceSynchronize();
   drop_graph(bt);
+  for (fde_plan pl : bt->plans)
+    if (pl) fde_destroy(pl);
+  for (hipStream_t w : bt->wstreams) (void)hipStreamDestroy(w);
   if (bt->cap) (void)hipStreamDestroy(bt->cap);
   for (void* q : bt->allocs) (void)hipFree(q);
   delete bt;
@@ -249,7 +265,8 @@ fde_status enqueue(fde_batch bt, const fde_batch_cfg& c, int mode, const double*
   a.inst = bt->dinst;
   a.count = bt->count;
   a.mode = mode;
-  a.order = c.lpt ? bt->order_lpt : bt->order_nat;
+  a.order = bt->order_q;
+  a.nq = bt->nq;
   a.queue = bt->queue;
   a.tw64 = bt->tw64;
   a.tw32 = bt->tw32;
@@ -284,10 +301,14 @@ fde_status ensure_info(fde_batch bt, long entries) {
   return FDE_OK;
 }
 
-fde_status collect(fde_batch bt, long entries, fde_info* out, double seconds, hipStream_t st) {
+fde_status collect(fde_batch bt, long entries, fde_info* out, double seconds, hipStream_t st,
+                   const std::vector<std::pair<long, Info>>* plan_info = nullptr) {
   bt->hinfo.resize(entries);
   HIPCHK(hipMemcpyAsync(bt->hinfo.data(), bt->info, entries * sizeof(Info), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  if (plan_info)
+    for (const auto& e : *plan_info) bt->hinfo[e.first] = e.second;
+  for (long e = 0; e < entries; ++e) bt->last_iters[e % bt->count] = bt->hinfo[e].iters;
   bool nonfinite = false, notconv = false;
   for (long e = 0; e < entries; ++e) {
     const Info& r = bt->hinfo[e];
@@ -305,6 +326,109 @@ fde_status collect(fde_batch bt, long entries, fde_info* out, double seconds, hi
   }
   if (nonfinite) return fail(FDE_ENONFINITE, "a right-hand side or residual became non-finite");
   if (notconv) return fail(FDE_ENOTCONV, "some instances did not reach the tolerance");
+  return FDE_OK;
+}
+
+constexpr int SPLIT_WORKERS = 4;   // worker threads (and streams) of the plan-path instances
+
+// Estimated work of instance i: its per-iteration model times the iterations
+// of its last solve (1 before any).
+double est_work(const fde_batch bt, int i) {
+  return (bt->last_iters[i] > 0 ? (double)bt->last_iters[i] : 1.0) * bt->cost[i];
+}
+
+// The split set of configuration c (its c.split instances of largest
+// estimated work, largest first), their plans (built here, on the calling
+// thread, before any launch of this call), the worker streams, and the queue
+// order of the persistent launch without them (largest estimated work first
+// with c.lpt, else as given), copied to the device on `st`.
+fde_status prepare_queue(fde_batch bt, const fde_batch_cfg& c, hipStream_t st) {
+  const int count = bt->count;
+  const int k = std::max(0, std::min(c.split, count));
+  std::vector<int> idx(count);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return est_work(bt, a) > est_work(bt, b); });
+  bt->split_idx.assign(idx.begin(), idx.begin() + k);
+  std::vector<char> split(count, 0);
+  for (int i : bt->split_idx) split[i] = 1;
+  bt->hq.clear();
+  if (c.lpt) {
+    for (int i : idx)
+      if (!split[i]) bt->hq.push_back(i);
+  } else {
+    for (int i = 0; i < count; ++i)
+      if (!split[i]) bt->hq.push_back(i);
+  }
+  bt->nq = (int)bt->hq.size();
+  if (bt->nq) HIPCHK(hipMemcpyAsync(bt->order_q, bt->hq.data(), bt->nq * sizeof(int), hipMemcpyHostToDevice, st));
+  for (int i : bt->split_idx)
+    if (!bt->plans[i]) {
+      const fde_params q = bt->p[i];
+      TRY(fde_assemble(&q, bt->hdp[i], bt->hdm[i], nullptr, nullptr, st, &bt->plans[i]));
+    }
+  const int nw = std::min(k, SPLIT_WORKERS);
+  while ((int)bt->wstreams.size() < nw) {
+    hipStream_t w = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&w, hipStreamNonBlocking));
+    bt->wstreams.push_back(w);
+  }
+  HIPCHK(hipStreamSynchronize(st));   // the host copy of the order stays valid until here
+  return FDE_OK;
+}
+
+// The split instances on the plan path, by SPLIT_WORKERS threads (the calling
+// thread is one of them), each on its own stream, dealt largest work first:
+// `steps` implicit steps from x (b = rhs(x), solve from x; step_mode) or one
+// solve of b.  Their per-step results go to `res` as (info slot, Info).
+fde_status run_split(fde_batch bt, const double* b, double* x, int steps, bool step_mode,
+                     std::vector<std::pair<long, Info>>& res) {
+  const int k = (int)bt->split_idx.size();
+  if (!k) return FDE_OK;
+  const int nw = std::min(k, (int)bt->wstreams.size());
+  std::vector<fde_status> status(nw, FDE_OK);
+  std::vector<std::string> errs(nw);
+  std::vector<std::vector<std::pair<long, Info>>> out(nw);
+  auto work = [&](int w) {
+    if (hipSetDevice(bt->dev) != hipSuccess) {
+      status[w] = FDE_EHIP;
+      errs[w] = "hipSetDevice failed in a worker";
+      return;
+    }
+    hipStream_t s = bt->wstreams[w];
+    for (int j = w; j < k; j += nw) {
+      const int i = bt->split_idx[j];
+      fde_plan pl = bt->plans[i];
+      const long off = bt->off[i];
+      for (int t = 0; t < steps; ++t) {
+        if (step_mode) {
+          const fde_status r = fde_rhs(pl, x + off, nullptr, bt->hb[i], s);
+          if (r != FDE_OK) {
+            status[w] = r;
+            errs[w] = fde_last_error();
+            return;
+          }
+        }
+        fde_info fi{};
+        const fde_status r = fde_solve(pl, step_mode ? bt->hb[i] : b + off, x + off, &fi, s);
+        if (r < 0 && r != FDE_ENONFINITE) {
+          status[w] = r;
+          errs[w] = fde_last_error();
+          return;
+        }
+        Info in{fi.iters, fi.inner_iters, fi.restarts, fi.converged, r == FDE_ENONFINITE ? 1 : 0, 0,
+                fi.relres_true, fi.relres_est};
+        out[w].push_back({(long)t * bt->count + i, in});
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  for (int w = 1; w < nw; ++w) th.emplace_back(work, w);
+  work(0);
+  for (auto& t : th) t.join();
+  for (int w = 0; w < nw; ++w) {
+    if (status[w] != FDE_OK) return fail(status[w], "plan-path instance: %s", errs[w].c_str());
+    res.insert(res.end(), out[w].begin(), out[w].end());
+  }
   return FDE_OK;
 }
 
@@ -343,6 +467,12 @@ fde_status assemble_impl(const fde_params* ps, int count, const double* dp, cons
   TRY(balloc(bt, &arena, base[count]));
   HIPCHK(hipMemsetAsync(arena, 0, base[count], st));
   std::vector<Inst> hinst(count);
+  bt->hdp.assign(count, nullptr);
+  bt->hdm.assign(count, nullptr);
+  bt->hb.assign(count, nullptr);
+  bt->plans.assign(count, nullptr);
+  bt->last_iters.assign(count, 0);
+  bt->dev = dev;
   std::vector<unsigned char> img;
   for (int i = 0; i < count; ++i) {
     const fde_params& p = ps[i];
@@ -495,6 +625,9 @@ fde_status assemble_impl(const fde_params* ps, int count, const double* dp, cons
       I.t32.ar = d32(5); I.t32.cr = d32(6); I.t32.ra = d32(7); I.t32.rb = d32(8); I.t32.rc = d32(9);
       I.t32.ty = d32(10);
     }
+    bt->hdp[i] = I.t64.dp;
+    bt->hdm[i] = I.t64.dm;
+    bt->hb[i] = reinterpret_cast<double*>(a0 + L.b);
     I.V = reinterpret_cast<double*>(a0 + L.V);
     I.Z = reinterpret_cast<double*>(a0 + L.Z);
     I.b = reinterpret_cast<double*>(a0 + L.b);
@@ -530,26 +663,21 @@ fde_status assemble_impl(const fde_params* ps, int count, const double* dp, cons
     HIPCHK(hipMemcpy(bt->tw32, t32.data(), t32.size(), hipMemcpyHostToDevice));
   }
 
-  // queue orders: as given, and longest estimated work first
-  std::vector<int> nat(count), lpt(count);
-  std::iota(nat.begin(), nat.end(), 0);
-  std::vector<double> cost(count);
+  // per-iteration work model of each instance (the queue order's key, times
+  // the iterations of its last solve once known)
+  bt->cost.assign(count, 0.0);
   for (int i = 0; i < count; ++i) {
     const Geo g = geometry(ps[i]);
-    cost[i] = (double)g.n * (ps[i].restart + 8.0) + (double)g.Qs * g.logQs * (g.blue ? 4.0 : 2.0) +
-              3.0 * (double)g.Qt * g.logQt;
+    bt->cost[i] = (double)g.n * (ps[i].restart + 8.0) + (double)g.Qs * g.logQs * (g.blue ? 4.0 : 2.0) +
+                  3.0 * (double)g.Qt * g.logQt;
   }
-  lpt = nat;
-  std::stable_sort(lpt.begin(), lpt.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-  TRY(balloc(bt, &bt->order_nat, count));
-  TRY(balloc(bt, &bt->order_lpt, count));
-  HIPCHK(hipMemcpy(bt->order_nat, nat.data(), count * sizeof(int), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(bt->order_lpt, lpt.data(), count * sizeof(int), hipMemcpyHostToDevice));
+  TRY(balloc(bt, &bt->order_q, count));
   TRY(balloc(bt, &bt->queue, 1));
   TRY(balloc(bt, &bt->step, 1));
   TRY(ensure_info(bt, count));
-  bt->cfg = fde_batch_cfg{0, 2 * bt->cus, 1, 0.0};
+  bt->cfg = fde_batch_cfg{0, 2 * bt->cus, 1, 0.0, 0};
   HIPCHK(hipStreamCreateWithFlags(&bt->cap, hipStreamNonBlocking));
+  TRY(prepare_queue(bt, bt->cfg, st));
   HIPCHK(hipStreamSynchronize(st));
   return FDE_OK;
 }
@@ -602,10 +730,14 @@ extern "C" fde_status fde_batch_solve(fde_batch bt, const double* b, double* x, 
   if (!bt || !b || !x) return fail(FDE_EINVAL, "NULL argument");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const auto t0 = std::chrono::steady_clock::now();
+  TRY(prepare_queue(bt, bt->cfg, st));
   TRY(enqueue(bt, bt->cfg, MODE_SOLVE, b, x, nullptr, st));
+  std::vector<std::pair<long, Info>> pinfo;
+  const fde_status ws = run_split(bt, b, x, 1, false, pinfo);   // concurrently with the launch
   HIPCHK(hipStreamSynchronize(st));
+  TRY(ws);
   const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  return collect(bt, bt->count, info, sec, st);
+  return collect(bt, bt->count, info, sec, st, &pinfo);
 }
 
 // The batched operator launches are disabled: their first GPU run took a
@@ -641,12 +773,13 @@ extern "C" fde_status fde_batch_run(fde_batch bt, double* u, int steps, int use_
   if (steps < 1) return fail(FDE_EINVAL, "steps must be >= 1");
   hipStream_t st = static_cast<hipStream_t>(stream);
   TRY(ensure_info(bt, (long)steps * bt->count));
+  TRY(prepare_queue(bt, bt->cfg, st));
   HIPCHK(hipMemsetAsync(bt->step, 0, sizeof(int), st));
   const auto t0 = std::chrono::steady_clock::now();
   if (use_graph) {
     const fde_batch_cfg& c = bt->cfg;
     if (!bt->gexec || bt->gx != u || bt->gcfg.variant != c.variant || bt->gcfg.grid != c.grid ||
-        bt->gcfg.lpt != c.lpt) {
+        bt->gcfg.lpt != c.lpt || bt->gcfg.split != c.split) {
       drop_graph(bt);
       HIPCHK(hipStreamBeginCapture(bt->cap, hipStreamCaptureModeThreadLocal));
       const fde_status s = enqueue(bt, c, MODE_STEP, nullptr, u, bt->step, bt->cap);
@@ -666,47 +799,70 @@ extern "C" fde_status fde_batch_run(fde_batch bt, double* u, int steps, int use_
   } else {
     for (int s = 0; s < steps; ++s) TRY(enqueue(bt, bt->cfg, MODE_STEP, nullptr, u, bt->step, st));
   }
+  std::vector<std::pair<long, Info>> pinfo;
+  const fde_status ws = run_split(bt, nullptr, u, steps, true, pinfo);   // concurrently with the launches
   HIPCHK(hipStreamSynchronize(st));
+  TRY(ws);
   const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  return collect(bt, (long)steps * bt->count, info, sec, st);
+  return collect(bt, (long)steps * bt->count, info, sec, st, &pinfo);
+}
+
+// One time step of configuration c from u (copied to the tuning state), wall
+// time in milliseconds (the persistent launch and the plan-path instances).
+static fde_status tune_trial(fde_batch bt, const fde_batch_cfg& c, const double* u, hipStream_t st, double* ms) {
+  TRY(prepare_queue(bt, c, st));
+  HIPCHK(hipMemcpyAsync(bt->tune_x, u, bt->total * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const auto t0 = std::chrono::steady_clock::now();
+  TRY(enqueue(bt, c, MODE_STEP, nullptr, bt->tune_x, nullptr, st));
+  std::vector<std::pair<long, Info>> pinfo;
+  const fde_status ws = run_split(bt, nullptr, bt->tune_x, 1, true, pinfo);
+  HIPCHK(hipStreamSynchronize(st));
+  TRY(ws);
+  *ms = 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return FDE_OK;
 }
 
 extern "C" fde_status fde_batch_tune(fde_batch bt, const double* u, void* stream, fde_batch_cfg* chosen) {
   if (!bt || !u) return fail(FDE_EINVAL, "NULL argument");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (!bt->tune_x) TRY(balloc(bt, &bt->tune_x, (size_t)bt->total));
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
-  fde_batch_cfg best{bt->cfg.variant, bt->cfg.grid, bt->cfg.lpt, 1e300};
-  std::vector<int> grids = {bt->cus, 2 * bt->cus};
-  fde_status rs = FDE_OK;
-  for (int v = 0; v < VARIANTS_ENABLED && rs == FDE_OK; ++v)
-    for (int gi = 0; gi < (int)grids.size() && rs == FDE_OK; ++gi)
-      for (int lp = 1; lp >= 0 && rs == FDE_OK; --lp) {
-        const fde_batch_cfg c{v, grids[gi], lp, 0.0};
+  fde_batch_cfg best{bt->cfg.variant, bt->cfg.grid, bt->cfg.lpt, 1e300, 0};
+  // launch configurations, every instance in the persistent launch
+  const std::vector<int> grids = {bt->cus, 2 * bt->cus};
+  for (int v = 0; v < VARIANTS_ENABLED; ++v)
+    for (int grid : grids)
+      for (int lp = 1; lp >= 0; --lp) {
+        const fde_batch_cfg c{v, grid, lp, 0.0, 0};
         double ms = 1e300;
-        for (int rep = 0; rep < 2 && rs == FDE_OK; ++rep) {
-          if (hipMemcpyAsync(bt->tune_x, u, bt->total * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess ||
-              hipEventRecord(e0, st) != hipSuccess) {
-            rs = fail(FDE_EHIP, "tuning copy failed");
-            break;
-          }
-          rs = enqueue(bt, c, MODE_STEP, nullptr, bt->tune_x, nullptr, st);
-          if (rs != FDE_OK) break;
-          float t = 0.0f;
-          if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-              hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
-            rs = fail(FDE_EHIP, "tuning timing failed");
-            break;
-          }
-          ms = std::min(ms, (double)t);
+        for (int rep = 0; rep < 2; ++rep) {
+          double t = 0.0;
+          TRY(tune_trial(bt, c, u, st, &t));
+          ms = std::min(ms, t);
         }
-        if (ms < best.ms) best = fde_batch_cfg{v, grids[gi], lp, ms};
+        if (ms < best.ms) best = fde_batch_cfg{v, grid, lp, ms, 0};
       }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  TRY(rs);
+  // the iterations of every instance (the trials' per-instance results) set the work estimates
+  bt->hinfo.resize(bt->count);
+  HIPCHK(hipMemcpyAsync(bt->hinfo.data(), bt->info, bt->count * sizeof(Info), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int i = 0; i < bt->count; ++i) bt->last_iters[i] = bt->hinfo[i].iters;
+  // then the instances of largest estimated work on the plan path
+  for (int k : {4, 8, 16, 32, 64}) {
+    if (k >= bt->count) break;
+    fde_batch_cfg c = best;
+    c.split = k;
+    double ms = 1e300, t = 0.0;
+    TRY(tune_trial(bt, c, u, st, &t));   // first run of new plans: not timed
+    for (int rep = 0; rep < 2; ++rep) {
+      TRY(tune_trial(bt, c, u, st, &t));
+      ms = std::min(ms, t);
+    }
+    if (ms < best.ms) {
+      best = c;
+      best.ms = ms;
+    }
+  }
   bt->cfg = best;
   drop_graph(bt);
   if (chosen) *chosen = best;
@@ -725,7 +881,8 @@ extern "C" fde_status fde_batch_set_cfg(fde_batch bt, const fde_batch_cfg* cfg) 
     return fail(FDE_EINVAL, "variant must be in 0..%d", FDE_BATCH_VARIANTS - 1);
   if (cfg->variant >= VARIANTS_ENABLED) return fail(FDE_EUNSUPPORTED, "launch variant %d is disabled", cfg->variant);
   if (cfg->grid < 1) return fail(FDE_EINVAL, "grid must be >= 1");
-  bt->cfg = fde_batch_cfg{cfg->variant, cfg->grid, cfg->lpt ? 1 : 0, 0.0};
+  if (cfg->split < 0 || cfg->split > bt->count) return fail(FDE_EINVAL, "split must be in 0..%d", bt->count);
+  bt->cfg = fde_batch_cfg{cfg->variant, cfg->grid, cfg->lpt ? 1 : 0, 0.0, cfg->split};
   drop_graph(bt);
   return FDE_OK;
 }

@@ -93,7 +93,8 @@ enum : int {
 
 struct Args {
   const Inst* inst;
-  int count, mode;
+  int count, mode;        // count: instances in the batch (the stride of the per-step info)
+  int nq, pad2;           // queue length: the first nq entries of `order` are solved here
   const int* order;       // instances in the order the queue hands them out
   unsigned* queue;        // ticket counter, zero at launch
   const cx<double>* tw64; // exp(-2 pi i m/TW), m < TW = 2^logTW
@@ -886,7 +887,7 @@ __global__ void __launch_bounds__(NT, BATCH_WAVES_PER_EU) batch_kernel(Args a) {
     __syncthreads();
     const int t = sh.ticket;
     __syncthreads();
-    if (t >= a.count) break;
+    if (t >= a.nq) break;
     const int idx = a.order[t];
     const Inst& I = a.inst[idx];
     if (a.mode >= MODE_MATVEC) {

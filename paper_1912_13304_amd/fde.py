@@ -77,7 +77,8 @@ class FdeInfo(ctypes.Structure):
 
 
 class FdeBatchCfg(ctypes.Structure):
-    _fields_ = [("variant", ctypes.c_int), ("grid", ctypes.c_int), ("lpt", ctypes.c_int), ("ms", ctypes.c_double)]
+    _fields_ = [("variant", ctypes.c_int), ("grid", ctypes.c_int), ("lpt", ctypes.c_int), ("ms", ctypes.c_double),
+                ("split", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -398,8 +399,8 @@ class Batch:
         _check(load().fde_batch_get_cfg(self.handle, ctypes.byref(c)))
         return c
 
-    def set_cfg(self, variant, grid, lpt=1):
-        c = FdeBatchCfg(int(variant), int(grid), int(lpt), 0.0)
+    def set_cfg(self, variant, grid, lpt=1, split=0):
+        c = FdeBatchCfg(int(variant), int(grid), int(lpt), 0.0, int(split))
         _check(load().fde_batch_set_cfg(self.handle, ctypes.byref(c)))
 
     def close(self):

@@ -258,6 +258,49 @@ def test_batch_edge_cases():
         assert infos[0].iters == 2 and not infos[0].converged
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_split_to_plan_path(precision):
+    """The instances of largest estimated work taken out of the persistent
+    launch and solved on the plan path by worker threads (split = 3 of 8,
+    any n): every instance still mirrors the oracle (float64) or meets the
+    tolerance within Varah's bound (mixed), in a solve and in graph-replayed
+    time steps; the split instances are the largest ones."""
+    fde = need_gpu()
+    sizes = [(9000, 1.2), (255, 1.5), (3000, 1.3), (12000, 1.15), (77, 1.9), (6000, 1.4), (1000, 1.6), (5000, 1.25)]
+    probs = [inst(n, a, 1500 + n) for n, a in sizes]
+    kw = dict(precision=fde.MIXED, inner_steps=0) if precision == "mixed" else {}
+    with fde.Batch(probs, **kw) as bt:
+        bt.set_cfg(0, 64, 1, split=3)
+        assert bt.get_cfg().split == 3
+        b = bt.pack([FDESystem.from_problem(p).rhs(p.u0) for p in probs])
+        x = bt.pack([p.u0 for p in probs])
+        infos = bt.solve(b, x)
+        xs = bt.unpack(x)
+        for p, xg, ig in zip(probs, xs, infos):
+            if precision == "fp64":
+                check_fp64(p, xg, ig)
+            else:
+                s, bb, xo, io = oracle_solve(p)
+                assert ig.converged
+                rg, ro = bb - s.matvec(xg), bb - s.matvec(xo)
+                assert np.linalg.norm(rg) <= 1e-8 * (1 + 1e-6) * np.linalg.norm(bb)
+                assert np.abs(xg - xo).max() <= (np.abs(rg).max() + np.abs(ro).max()) / s.nu
+        # time steps (graph) with the split: each step against the oracle from the previous state
+        us = bt.pack([p.u0 for p in probs])
+        prev = bt.unpack(us)
+        for step in range(2):
+            info = bt.run(us, 1, use_graph=True)[0]
+            cur = bt.unpack(us)
+            for p, u0, xg, ig in zip(probs, prev, cur, info):
+                q = fi.variable_1d(n=p.n[0], alpha=p.alpha[0], steps=1)
+                q.dplus, q.dminus, q.u0 = p.dplus, p.dminus, u0
+                if precision == "fp64":
+                    check_fp64(q, xg, ig)
+                else:
+                    assert ig.converged and ig.relres_true <= 1e-8
+            prev = cur
+
+
 def test_batch_tune():
     fde = need_gpu()
     probs = fi.batched_1d(count=24, seed=4, nmax=4095, steps=1)
@@ -266,9 +309,9 @@ def test_batch_tune():
         before = u.clone()
         c = bt.tune(u)
         assert torch.equal(u, before)
-        assert 0 <= c.variant < fde.BATCH_VARIANTS and c.grid >= 1 and c.ms > 0
+        assert 0 <= c.variant < fde.BATCH_VARIANTS and c.grid >= 1 and c.ms > 0 and 0 <= c.split < len(probs)
         got = bt.get_cfg()
-        assert (got.variant, got.grid, got.lpt) == (c.variant, c.grid, c.lpt)
+        assert (got.variant, got.grid, got.lpt, got.split) == (c.variant, c.grid, c.lpt, c.split)
         infos = bt.run(u, 1)
     xs = bt.unpack(u)
     for p, xg, ig in zip(probs, xs, infos[0]):

@@ -530,7 +530,8 @@ def test_plan_buffers_reused_and_released():
 
 
 @pytest.mark.parametrize("case", ["2d-1023-fp64", "2d-1023-mixed", "2d-15x4095", "1d-65535-fp64",
-                                  "1d-65535-mixed", "1d-1023-pcg"])
+                                  "1d-65535-mixed", "1d-1023-pcg", "1d-40000-chirp", "1d-40000-chirp-mixed",
+                                  "2d-300x200-dense-mixed"])
 def test_plan_bytes_matches_device_allocation(case):
     """fde_plan_bytes (the admission figure of the server) agrees with what
     assembly takes from the device, measured with the memory cache empty
@@ -538,7 +539,9 @@ def test_plan_bytes_matches_device_allocation(case):
     fde = need_gpu()
     p = {"2d-1023-fp64": lambda: prob2d(1023, 1023), "2d-1023-mixed": lambda: prob2d(1023, 1023),
          "2d-15x4095": lambda: prob2d(15, 4095), "1d-65535-fp64": lambda: prob1d(65535),
-         "1d-65535-mixed": lambda: prob1d(65535), "1d-1023-pcg": lambda: fi.constant_1d(n=1023)}[case]()
+         "1d-65535-mixed": lambda: prob1d(65535), "1d-1023-pcg": lambda: fi.constant_1d(n=1023),
+         "1d-40000-chirp": lambda: prob1d(40000), "1d-40000-chirp-mixed": lambda: prob1d(40000),
+         "2d-300x200-dense-mixed": lambda: prob2d(300, 200)}[case]()
     kw = dict(precision=fde.MIXED) if case.endswith("mixed") else {}
     fde.fde_release_cache()
     torch.cuda.synchronize()
