@@ -138,7 +138,14 @@ fde_status fde_tau_apply(fde_plan plan, const double* v, double* z, void* stream
 /* Solves M x = b (eq. linsystem).  b: device, length N.  x: device, length
    N, holds the starting vector on entry and the solution on return.  info:
    host pointer or NULL.  Synchronises `stream`.  b = 0 returns x = 0 with 0
-   iterations.  FDE_ENONFINITE when b or a residual is not finite. */
+   iterations.  FDE_ENONFINITE when b or a residual is not finite.
+   Residual history: with the environment variable FDE_TRACE set to 1
+   (standard error) or to a file name (appended to), the solve writes
+     fde_trace solve=<k> solver=<gmres|pcg> kind=<est|true> iter=<i> relres=<v>
+   per iteration (kind=est: the solver's estimate of ||b - M x|| / ||b||) and
+   per true-residual check (kind=true); the one-workgroup 1D PCG solve writes
+   its final values only.  Tracing reads the state back every cycle (PCG:
+   every iteration) and is not meant for timing. */
 fde_status fde_solve(fde_plan plan, const double* b, double* x, fde_info* info, void* stream);
 
 /* Right-hand side of one time step (Section 1.2, eq. matrixform; Section 1.4

@@ -109,11 +109,11 @@ def fgmres(A, b, P, x0=None, restart=30, tol=1e-8, maxit=100000, history=False):
     return x, info
 
 
-def pcg(A, b, P, x0=None, tol=1e-10, maxit=100000):
+def pcg(A, b, P, x0=None, tol=1e-10, maxit=100000, history=False):
     b = np.asarray(b, dtype=np.float64).reshape(-1)
     N = b.size
     x = np.zeros(N) if x0 is None else np.array(x0, dtype=np.float64).reshape(-1)
-    info = dict(iters=0, restarts=0, converged=False, relres_true=0.0, relres_est=0.0)
+    info = dict(iters=0, restarts=0, converged=False, relres_true=0.0, relres_est=0.0, hist=[])
     bnorm = np.linalg.norm(b)
     if bnorm == 0.0:
         info["converged"] = True
@@ -135,6 +135,8 @@ def pcg(A, b, P, x0=None, tol=1e-10, maxit=100000):
         info["iters"] += 1
         rn = np.linalg.norm(r)
         info["relres_est"] = rn / bnorm
+        if history:
+            info["hist"].append(rn / bnorm)
         if rn <= tol * bnorm:
             rt = b - A(x)
             tn = np.linalg.norm(rt)

@@ -1519,6 +1519,66 @@ static void residual(fde_plan pl, const double* b, const double* x, hipStream_t 
   norm_red<double>(pl, b, tmp, pl->V, pl->ks, EP_RESID, st);
 }
 
+// ---------------------------------------------------------------------------
+// Residual-history trace.  With FDE_TRACE set to "1" (standard error) or to a
+// file name (appended to), every solve writes one line per iteration with the
+// solver's residual estimate and one per true-residual check, both relative
+// to ||b||:
+//   fde_trace solve=<k> solver=<gmres|pcg> kind=<est|true> iter=<i> relres=<v>
+// The FGMRES estimates after the iterations of a cycle are rebuilt from the
+// cycle's starting residual and the sines of its Givens rotations,
+// beta |s_0| ... |s_j|, in the order the device formed them, so they equal
+// the device's values.  The one-workgroup PCG solve reports its final
+// estimate and true residual only.  Tracing adds host reads per cycle (PCG:
+// per iteration) and is meant for inspection, not for timing.
+// ---------------------------------------------------------------------------
+struct Trace {
+  FILE* f = nullptr;
+  bool own = false;
+  long id = 0;
+  const char* solver = "";
+  Trace(const char* solver_name) : solver(solver_name) {
+    static std::mutex mu;
+    static long next = 0;
+    const char* e = std::getenv("FDE_TRACE");
+    if (!e || !*e || std::strcmp(e, "0") == 0) return;
+    if (std::strcmp(e, "1") == 0) {
+      f = stderr;
+    } else {
+      f = std::fopen(e, "a");
+      own = f != nullptr;
+    }
+    std::lock_guard<std::mutex> g(mu);
+    id = next++;
+  }
+  ~Trace() {
+    if (own) std::fclose(f);
+  }
+  bool on() const { return f != nullptr; }
+  void line(const char* kind, int iter, double relres) const {
+    if (f) std::fprintf(f, "fde_trace solve=%ld solver=%s kind=%s iter=%d relres=%.17g\n", id, solver, kind, iter, relres);
+  }
+};
+
+// Estimates after the iterations iters0+1 .. iters of the cycle that just
+// ended (its Givens sines are still in the state), then its true residual.
+static fde_status trace_cycle(fde_plan pl, const Trace& tr, double beta0, int iters0, hipStream_t st) {
+  const KState h = *pl->hks;
+  const int k = h.iters - iters0;
+  if (k > 0) {
+    std::vector<double> sn(k);
+    HIPCHK(hipMemcpyAsync(sn.data(), pl->ks->sn, k * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double g = beta0;
+    for (int j = 0; j < k; ++j) {
+      g = -sn[j] * g;
+      tr.line("est", iters0 + j + 1, std::fabs(g) / h.bnorm);
+    }
+  }
+  tr.line("true", h.iters, h.beta / h.bnorm);
+  return FDE_OK;
+}
+
 static fde_status solve_gmres(fde_plan pl, const double* b, double* x, fde_info* info, hipStream_t st) {
   const long N = pl->N;
   KState* ks = pl->ks;
@@ -1536,8 +1596,12 @@ static fde_status solve_gmres(fde_plan pl, const double* b, double* x, fde_info*
     if (info) *info = fde_info{0, 0, 0, 1, 0.0, 0.0, 0.0};
     return FDE_OK;
   }
+  Trace tr("gmres");
+  tr.line("true", 0, pl->hks->beta / pl->hks->bnorm);
   int restarts = 0;
   while (!pl->hks->conv && !pl->hks->nonfinite && pl->hks->iters < pl->p.maxit) {
+    const double beta0 = pl->hks->beta;
+    const int iters0 = pl->hks->iters;
     pl->hstat[0] = 0.0;
     for (int j = 0; j < pl->m; ++j) {
       if (j >= 2) {
@@ -1553,6 +1617,7 @@ static fde_status solve_gmres(fde_plan pl, const double* b, double* x, fde_info*
     residual(pl, b, x, st);
     HIPCHK(hipGetLastError());
     TRY(read_header(pl, ks, st));
+    if (tr.on()) TRY(trace_cycle(pl, tr, beta0, iters0, st));
     if (!pl->hks->conv) ++restarts;
   }
   const KState h = *pl->hks;
@@ -1653,6 +1718,11 @@ static fde_status solve_pcg_one_workgroup(fde_plan pl, const double* b, double* 
     if (info) *info = fde_info{0, 0, 0, 1, 0.0, 0.0, 0.0};
     return FDE_OK;
   }
+  {
+    Trace tr("pcg");
+    tr.line("est", h.iters, h.est / h.bnorm);
+    tr.line("true", h.iters, h.beta / h.bnorm);
+  }
   if (info) {
     info->iters = h.iters;
     info->inner_iters = 0;
@@ -1690,6 +1760,8 @@ static fde_status solve_pcg(fde_plan pl, const double* b, double* x, fde_info* i
     return FDE_OK;
   }
   const int G = red_grid(N, (long)RED_THREADS * 8);
+  Trace tr("pcg");
+  tr.line("true", 0, pl->hks->beta / pl->hks->bnorm);
   int restarts = 0;
   while (!pl->hks->conv && !pl->hks->nonfinite && pl->hks->iters < pl->p.maxit) {
     // (re)start: z = P^{-1} r, rz = r.z, p = z
@@ -1712,12 +1784,20 @@ static fde_status solve_pcg(fde_plan pl, const double* b, double* x, fde_info* i
       dot_red<double>(pl, r, z, ks, EP_CG_RZ, st, skip);
       hipLaunchKernelGGL(cg_direction_kernel, dim3(ew_grid(N)), dim3(256), 0, st, p, z, N, ks, skip);
       HIPCHK(hipEventRecord(pl->ev[it & 3], st));
+      if (tr.on()) {
+        const int before = pl->hks->iters;
+        TRY(read_header(pl, ks, st));
+        if (pl->hks->iters == before) break;   // the iteration was skipped: the solve had stopped
+        tr.line("est", pl->hks->iters, pl->hks->est / pl->hks->bnorm);
+        if (pl->hks->done) break;
+      }
     }
     // true residual
     matvec_only<double>(pl, x, q, pl->nu, 1.0, st, nullptr);
     norm_red<double>(pl, b, q, r, ks, EP_RESID, st);
     HIPCHK(hipGetLastError());
     TRY(read_header(pl, ks, st));
+    tr.line("true", pl->hks->iters, pl->hks->beta / pl->hks->bnorm);
     if (!pl->hks->conv) ++restarts;
   }
   const KState h = *pl->hks;

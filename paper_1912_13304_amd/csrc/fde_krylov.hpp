@@ -79,22 +79,32 @@ __device__ __forceinline__ void reduce_parts(const double* part, int G, int nq, 
 // Scalar epilogues (run by thread 0 of the last workgroup).
 // ---------------------------------------------------------------------------
 
+// Value of v in lane i of the wavefront (i uniform across the wavefront).
+__device__ __forceinline__ double lane_value(double v, int i) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), i);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), i);
+  return __hiloint2double(hi, lo);
+}
+
 // New Hessenberg column j from h = h1 + h2 (i <= j) and hn = ||w||; applies
 // the earlier rotations, forms rotation j, updates g and the residual
-// estimate.  Run by the 64 lanes of one wavefront: lane i holds h_i, and the
-// rotation of rows (i, i+1) reads both entries with readlane.
+// estimate.  Run by the 64 lanes of one wavefront: lane i holds h_i and the
+// earlier rotation i (all loaded at once), and the rotation of rows (i, i+1)
+// reads its four values with readlane.
 __device__ inline void givens_column_wave(KState* ks, int j, double hn) {
   const int lane = threadIdx.x & 63;
   double h = 0.0;
   if (lane <= j) h = ks->h1[lane] + ks->h2[lane];
   else if (lane == j + 1) h = hn;
+  const double cl = lane < j ? ks->cs[lane] : 0.0;
+  const double sl = lane < j ? ks->sn[lane] : 0.0;
   for (int i = 0; i < j; ++i) {
-    const double c = ks->cs[i], s = ks->sn[i];
-    const double a = __shfl(h, i, 64), b = __shfl(h, i + 1, 64);
+    const double c = lane_value(cl, i), s = lane_value(sl, i);
+    const double a = lane_value(h, i), b = lane_value(h, i + 1);
     if (lane == i) h = c * a + s * b;
     else if (lane == i + 1) h = -s * a + c * b;
   }
-  const double a = __shfl(h, j, 64);
+  const double a = lane_value(h, j);
   const double rho = hypot(a, hn);
   double c = 1.0, s = 0.0;
   if (rho != 0.0) {
