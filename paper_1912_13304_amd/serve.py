@@ -15,6 +15,11 @@ and the current and previous time levels.
 Results do not depend on the mix: every reduction in the library sums in a
 fixed order within one solve, so a request's iterates are the same alone and
 in any mix.
+
+A request can be cancelled by name: a pending one is dropped at once, a
+running one stops before its next time step (the step in flight finishes),
+and either comes back as a result with status CANCELLED and the steps it
+completed.
 """
 from __future__ import annotations
 
@@ -46,11 +51,16 @@ class Result:
         return self.status == 0
 
     @property
+    def cancelled(self) -> bool:
+        return self.status == CANCELLED
+
+    @property
     def latency(self) -> float:
         return self.finish - self.arrival
 
 
 AUTO = "auto"
+CANCELLED = -100   # Result.status of a cancelled request (a server status, not a library one)
 INNER_2D = 16   # float32 inner GMRES steps of a 2D mixed request
 
 
@@ -80,11 +90,13 @@ def footprint(problem, **kw) -> int:
     return fde.fde_plan_bytes(p) + 3 * problem.N * 8
 
 
-def run_job(problem, stream=None, keep_state=False, **kw):
+def run_job(problem, stream=None, keep_state=False, stop=None, **kw):
     """One time-stepping job on the current device: assemble, then for every
     step b = rhs(u), solve M u_new = b from u_new = u.  Returns (infos, u);
     keep_state="all" returns (infos, u, host copies of the state after every
-    step) instead (checking only: a host copy per step)."""
+    step) instead (checking only: a host copy per step).  `stop`, if given, is
+    called before each step; when it returns true the job ends there (infos
+    then covers the steps done)."""
     import torch
     dev = torch.device("cuda", torch.cuda.current_device())
     T = lambda a: None if a is None else torch.as_tensor(a, dtype=torch.float64, device=dev).reshape(-1).contiguous()
@@ -97,6 +109,8 @@ def run_job(problem, stream=None, keep_state=False, **kw):
     infos, states = [], []
     try:
         for _ in range(problem.steps):
+            if stop is not None and stop():
+                break
             fde.fde_rhs(handle, u, None, b, stream=stream)
             x.copy_(u)
             infos.append(fde.fde_solve(handle, b, x, stream=stream))
@@ -125,6 +139,8 @@ class Server:
         self.in_use = 0.0
         self.closed = False
         self.results: List[Result] = []
+        self.running: set = set()      # names of the requests in service
+        self.cancel_flags: set = set()  # running requests asked to stop
         self.t0 = None
         self.threads = [threading.Thread(target=self._worker, args=(i,), daemon=True) for i in range(slots)]
 
@@ -140,6 +156,24 @@ class Server:
         with self.cv:
             self.pending.append((self.now() if arrival is None else arrival, problem))
             self.cv.notify_all()
+
+    def cancel(self, name: str) -> bool:
+        """Cancels the request `name` (the first pending one of that name, else
+        a running one).  Returns False when no such request is pending or
+        running (it finished already, or never came)."""
+        with self.cv:
+            for i, (arr, prob) in enumerate(self.pending):
+                if prob.name == name:
+                    self.pending.pop(i)
+                    t = self.now()
+                    self.results.append(Result(name, arr, t, t, prob.steps, status=CANCELLED,
+                                               error="cancelled before admission"))
+                    self.cv.notify_all()
+                    return True
+            if name in self.running:
+                self.cancel_flags.add(name)
+                return True
+            return False
 
     def close(self):
         with self.cv:
@@ -177,10 +211,13 @@ class Server:
                 return
             arr, prob, need = item
             start = self.now()
+            with self.cv:
+                self.running.add(prob.name)
+            stop = lambda: prob.name in self.cancel_flags
             try:
                 states = None
                 with torch.cuda.stream(stream):
-                    out = run_job(prob, stream=stream.cuda_stream, keep_state=self.keep_state,
+                    out = run_job(prob, stream=stream.cuda_stream, keep_state=self.keep_state, stop=stop,
                                   **request_kw(prob, self.solve_kw))
                     stream.synchronize()
                 infos, u = out[0], out[1]
@@ -189,6 +226,9 @@ class Server:
                 res = Result(prob.name, arr, start, self.now(), prob.steps,
                              [i.iters for i in infos], [i.inner_iters for i in infos],
                              [i.relres_true for i in infos], u, states)
+                if len(infos) < prob.steps:
+                    res.status = CANCELLED
+                    res.error = "cancelled after %d of %d steps" % (len(infos), prob.steps)
             except Exception as e:   # a failed request is reported; the slot keeps serving
                 stream.synchronize()
                 status = e.status if isinstance(e, fde.FdeError) else fde.FDE_EINVAL
@@ -196,6 +236,8 @@ class Server:
             finally:
                 self._release(need)
             with self.cv:
+                self.running.discard(prob.name)
+                self.cancel_flags.discard(prob.name)
                 self.results.append(res)
 
 
@@ -216,7 +258,7 @@ def serve_stream(arrivals, slots: int = 4, hbm_budget: float = 64e9, keep_state:
 
 def latency_stats(results, slots: Optional[int] = None) -> dict:
     """Latency percentiles and throughput over the completed requests; failed
-    requests are counted separately and contribute no solves.  With `slots`,
+    and cancelled requests are counted separately and contribute no solves.  With `slots`,
     also the utilisation: the fraction of the span during which at least one
     request was in service, the mean number in service, and the mean wait
     between arrival and admission."""
@@ -226,7 +268,9 @@ def latency_stats(results, slots: Optional[int] = None) -> dict:
     solves = sum(r.steps for r in done)
     t0 = min(r.arrival for r in results) if results else 0.0
     span = (max(r.finish for r in results) - t0) if results else 0.0
-    out = {"requests": len(results), "failed": len(results) - len(done), "solves": solves,
+    cancelled = sum(1 for r in results if r.cancelled)
+    out = {"requests": len(results), "failed": len(results) - len(done) - cancelled, "cancelled": cancelled,
+           "solves": solves,
            "p50_ms": float(1e3 * np.percentile(lat, 50)), "p99_ms": float(1e3 * np.percentile(lat, 99)),
            "mean_ms": float(1e3 * lat.mean()), "solves_per_s": solves / span if span > 0 else 0.0,
            "span_s": span}

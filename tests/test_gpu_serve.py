@@ -129,3 +129,46 @@ def test_served_results_against_oracle():
                     assert np.linalg.norm(rg) <= p.tol * (1 + 1e-6) * np.linalg.norm(b)
                     assert np.abs(xg - xo).max() <= (np.abs(rg).max() + np.abs(ro).max()) / s.nu
                 prev = xg
+
+
+def test_cancel_pending_and_running():
+    """A pending request is dropped at once; a running one stops before its
+    next step and returns the steps it completed, which equal the same steps
+    run alone; the other requests complete."""
+    import time
+    fde = need_gpu()
+    from paper_1912_13304_amd import serve
+    long = fi.variable_1d(n=4095, alpha=1.5, seed=3, steps=400)
+    long.name = "long"
+    others = []
+    for k, seed in enumerate((4, 5, 6)):
+        p = fi.variable_1d(n=1023, alpha=1.6, seed=seed, steps=2)
+        p.name = f"short{k}"
+        others.append(p)
+    srv = serve.Server(slots=1)
+    srv.start()
+    srv.submit(long)
+    for p in others:
+        srv.submit(p)
+    t0 = time.perf_counter()
+    while "long" not in srv.running:
+        assert time.perf_counter() - t0 < 60
+        time.sleep(0.001)
+    assert srv.cancel("short1")       # pending
+    assert srv.cancel("long")         # running
+    assert not srv.cancel("absent")
+    srv.close()
+    by = {r.name: r for r in srv.results}
+    assert len(srv.results) == 4
+    assert by["long"].cancelled and len(by["long"].iters) < long.steps
+    assert by["short1"].cancelled and by["short1"].iters == []
+    assert by["short0"].ok and by["short2"].ok
+    assert srv.in_use == 0.0 and not srv.running and not srv.cancel_flags   # slot and budget reclaimed
+    st = serve.latency_stats(srv.results, slots=1)
+    assert st["cancelled"] == 2 and st["failed"] == 0
+    assert st["solves"] == 2 * others[0].steps
+    done = len(by["long"].iters)
+    if done:
+        long.steps = done
+        infos, _ = serve.run_job(long)
+        assert by["long"].iters == [i.iters for i in infos]
