@@ -1653,7 +1653,7 @@ static bool pcg_one_workgroup(fde_plan pl) {
 }
 
 struct PcgArgs {
-  LineArgs<double> ta, ma, xa;
+  LineArgs<double> ta, ma;
   const double* b;
   double *x, *r, *p, *q, *z;
 };
@@ -1667,7 +1667,7 @@ static fde_status pcg1d_launch(fde_plan pl, const PcgArgs& g, hipStream_t st) {
   static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&pcg1d_kernel<LOGP>),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   HIPCHK(attr);
-  hipLaunchKernelGGL((pcg1d_kernel<LOGP>), dim3(1), dim3(pcg_threads(LOGP)), lds, st, g.ta, g.ma, g.xa, g.b, g.x, g.r,
+  hipLaunchKernelGGL((pcg1d_kernel<LOGP>), dim3(1), dim3(pcg_threads(LOGP)), lds, st, g.ta, g.ma, g.b, g.x, g.r,
                      g.p, g.q, g.z, (int)pl->N, pl->p.tol, pl->p.maxit, pl->ks);
   HIPCHK(hipGetLastError());
   return FDE_OK;
@@ -1697,8 +1697,6 @@ static fde_status solve_pcg_one_workgroup(fde_plan pl, const double* b, double* 
   g.ma.tscale = 1.0;
   g.ma.out = g.q;
   fill_line_args(pl->rows, g.ma);
-  g.xa = g.ma;   // q = M x
-  g.xa.in = x;
   switch (pl->rows.logP) {
     case 3: TRY(pcg1d_launch<3>(pl, g, st)); break;
     case 4: TRY(pcg1d_launch<4>(pl, g, st)); break;

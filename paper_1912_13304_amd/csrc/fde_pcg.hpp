@@ -32,21 +32,23 @@ __host__ __device__ constexpr int pcg_threads(int logP) {
   return rows_per_tile(1 << logP) * (1 << logP) / pcg_ept(logP);
 }
 
-// ta: z = P^{-1} r (in = r, out = z); ma: q = nu p + T-part (in = p, out = q);
-// xa: the same product of x (in = x, out = q).  Launched with one workgroup
-// of pcg_threads(LOGP) threads; the bound is that size so that the registers
-// of the three inlined line programs fit.
+// ta: z = P^{-1} r (in = r, out = z); ma: q = nu v + T-part v with out = q;
+// its input is x for a true residual and p within the iteration.  The steps
+// run as one loop with a single call site per line program (the Toeplitz
+// product's input chosen per pass), so that only two copies of the programs'
+// registers are live.  Launched with one workgroup of pcg_threads(LOGP)
+// threads; the bound is that size.
 template <int LOGP>
 __global__ void __launch_bounds__(pcg_threads(LOGP))
-pcg1d_kernel(LineArgs<double> ta, LineArgs<double> ma, LineArgs<double> xa, const double* b, double* x,
-             double* r, double* p, double* q, double* z, int n, double tol, int maxit, KState* ks) {
+pcg1d_kernel(LineArgs<double> ta, LineArgs<double> ma, const double* b, double* x, double* r, double* p, double* q,
+             double* z, int n, double tol, int maxit, KState* ks) {
   __shared__ double red[16];
   __shared__ double tot[1];
   const int tid = threadIdx.x, nt = blockDim.x;
   // Each inlined line program's address arithmetic depends on its tile; a
-  // tile index the compiler cannot see through keeps it from hoisting three
-  // copies of that arithmetic out of the loops, which would not fit in
-  // registers.  The value is always 0.
+  // tile index the compiler cannot see through keeps it from hoisting that
+  // arithmetic out of the loop, which would not fit in registers.  The value
+  // is always 0.
   auto tile0 = []() {
     int t = 0;
     asm volatile("" : "+s"(t));
@@ -73,36 +75,29 @@ pcg1d_kernel(LineArgs<double> ta, LineArgs<double> ma, LineArgs<double> xa, cons
     for (int e = tid; e < n; e += nt) x[e] = 0.0;
     conv = 1;
   } else if (!nonfinite) {
-    for (bool started = false;; started = true) {
-      line_body<double, false, LF_TOEP, LOGP, pcg_ept(LOGP)>(xa, tile0());   // q = M x
+    bool fresh = true;     // this pass's product is M x (a true residual); else M p
+    bool started = false;  // a true residual was taken before
+    bool first = true;     // the next direction is p = z (a (re)start)
+    for (;;) {
+      LineArgs<double> mv = ma;
+      mv.in = fresh ? x : p;
+      line_body<double, false, LF_TOEP, LOGP, pcg_ept(LOGP)>(mv, tile0());   // q = M x or q = M p
       __syncthreads();
-      double ss = 0.0;
-      for (int e = tid; e < n; e += nt) {
-        const double rv = b[e] - q[e];
-        r[e] = rv;
-        ss += rv * rv;
-      }
-      beta = sqrt(sum(ss));
-      conv = beta <= tolabs;
-      if (!isfinite(beta)) nonfinite = 1;
-      if (started && !conv) ++restarts;
-      if (conv || nonfinite || iters >= maxit) break;
-      // one (re)start of PCG from r
-      for (bool first = true;; first = false) {
-        line_body<double, false, LF_DST1 | LF_FDST2, LOGP, pcg_ept(LOGP)>(ta, tile0());   // z = P^{-1} r
-        __syncthreads();
-        const double rzn = dot(r, z);
-        if (first) {
-          betacg = 0.0;
-          for (int e = tid; e < n; e += nt) p[e] = z[e];
-        } else {
-          betacg = rz != 0.0 ? rzn / rz : 0.0;
-          for (int e = tid; e < n; e += nt) p[e] = z[e] + betacg * p[e];
+      if (fresh) {
+        double ss = 0.0;
+        for (int e = tid; e < n; e += nt) {
+          const double rv = b[e] - q[e];
+          r[e] = rv;
+          ss += rv * rv;
         }
-        rz = rzn;
-        __syncthreads();
-        line_body<double, false, LF_TOEP, LOGP, pcg_ept(LOGP)>(ma, tile0());   // q = M p
-        __syncthreads();
+        beta = sqrt(sum(ss));
+        conv = beta <= tolabs;
+        if (!isfinite(beta)) nonfinite = 1;
+        if (started && !conv) ++restarts;
+        started = true;
+        if (conv || nonfinite || iters >= maxit) break;
+        first = true;   // (re)start PCG from r
+      } else {
         pq = dot(p, q);
         alpha = rz / pq;
         double rr = 0.0;
@@ -115,8 +110,25 @@ pcg1d_kernel(LineArgs<double> ta, LineArgs<double> ma, LineArgs<double> xa, cons
         est = sqrt(sum(rr));
         ++iters;
         if (!isfinite(est)) nonfinite = 1;
-        if (est <= tolabs || nonfinite || iters >= maxit) break;   // uniform across the workgroup
+        if (est <= tolabs || nonfinite || iters >= maxit) {   // uniform across the workgroup
+          fresh = true;   // confirm with the true residual
+          continue;
+        }
       }
+      line_body<double, false, LF_DST1 | LF_FDST2, LOGP, pcg_ept(LOGP)>(ta, tile0());   // z = P^{-1} r
+      __syncthreads();
+      const double rzn = dot(r, z);
+      if (first) {
+        betacg = 0.0;
+        for (int e = tid; e < n; e += nt) p[e] = z[e];
+      } else {
+        betacg = rz != 0.0 ? rzn / rz : 0.0;
+        for (int e = tid; e < n; e += nt) p[e] = z[e] + betacg * p[e];
+      }
+      rz = rzn;
+      first = false;
+      fresh = false;
+      __syncthreads();
     }
   }
   if (tid == 0) {
