@@ -692,8 +692,22 @@ def main():
         "p99_served_latency_ms": served["p99_ms"] if served else None,
         "cpu_baseline": cpu,
         "parity": parity,
+        "process": process_state(),
     }
     print(json.dumps(out), flush=True)
+
+
+def process_state():
+    """What this process leaves running when it prints its line: child
+    processes (none are started: the served and batched legs use threads)
+    and live threads (the server's workers have been joined)."""
+    import threading
+    try:
+        import psutil
+        children = len(psutil.Process().children(recursive=True))
+    except ImportError:
+        children = None
+    return {"pid": os.getpid(), "child_processes": children, "threads": threading.active_count()}
 
 
 if __name__ == "__main__":
