@@ -132,7 +132,11 @@ def batched_leg(args, fi, fde, torch, np):
     for name, kw in forms.items():
         bt = fde.Batch(probs, **kw)
         u = bt.pack([p.u0 for p in probs])
-        if cfg is None:
+        if cfg is None and args.batch_cfg:
+            v, g, l, sp = (int(t) for t in args.batch_cfg.split(","))
+            cfg = {"variant": v, "grid": g, "lpt": l, "split": sp, "tuned": False}
+            bt.set_cfg(v, g, l, sp)
+        elif cfg is None:
             log(f"[bench] batched: tuning launch configuration")
             c = bt.tune(u)
             cfg = c.as_dict()
@@ -449,6 +453,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--batch-count", type=int, default=512, help="instances of the batched leg (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=2, help="timed time steps of the batched leg")
+    ap.add_argument("--batch-cfg", default="",
+                    help="variant,grid,lpt,split of the batched launch instead of the tuner's choice")
     ap.add_argument("--batch-plan-sample", type=int, default=512,
                     help="instances solved one plan at a time for the batched-vs-plan comparison")
     ap.add_argument("--only-batched", action="store_true",
