@@ -11,6 +11,8 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <thread>
@@ -809,6 +811,19 @@ extern "C" fde_status fde_batch_run(fde_batch bt, double* u, int steps, int use_
 
 // One time step of configuration c from u (copied to the tuning state), wall
 // time in milliseconds (the persistent launch and the plan-path instances).
+// With FDE_TRACE set (1: standard error, else a file name appended to), the
+// tuner writes one line per timed trial:
+//   fde_trace tune variant=<v> grid=<g> lpt=<l> split=<s> ms=<t>
+static void trace_trial(const fde_batch_cfg& c, double ms) {
+  const char* e = std::getenv("FDE_TRACE");
+  if (!e || !*e || std::strcmp(e, "0") == 0) return;
+  FILE* f = std::strcmp(e, "1") == 0 ? stderr : std::fopen(e, "a");
+  if (!f) return;
+  std::fprintf(f, "fde_trace tune variant=%d grid=%d lpt=%d split=%d ms=%.3f\n", c.variant, c.grid, c.lpt, c.split,
+               ms);
+  if (f != stderr) std::fclose(f);
+}
+
 static fde_status tune_trial(fde_batch bt, const fde_batch_cfg& c, const double* u, hipStream_t st, double* ms) {
   TRY(prepare_queue(bt, c, st));
   HIPCHK(hipMemcpyAsync(bt->tune_x, u, bt->total * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -838,6 +853,7 @@ extern "C" fde_status fde_batch_tune(fde_batch bt, const double* u, void* stream
         for (int rep = 0; rep < 2; ++rep) {
           double t = 0.0;
           TRY(tune_trial(bt, c, u, st, &t));
+          trace_trial(c, t);
           ms = std::min(ms, t);
         }
         if (ms < best.ms) best = fde_batch_cfg{v, grid, lp, ms, 0};
@@ -856,6 +872,7 @@ extern "C" fde_status fde_batch_tune(fde_batch bt, const double* u, void* stream
     TRY(tune_trial(bt, c, u, st, &t));   // first run of new plans: not timed
     for (int rep = 0; rep < 2; ++rep) {
       TRY(tune_trial(bt, c, u, st, &t));
+      trace_trial(c, t);
       ms = std::min(ms, t);
     }
     if (ms < best.ms) {
