@@ -100,6 +100,10 @@ struct fde_plan_s {
   float *Vf = nullptr, *t1f = nullptr, *t2f = nullptr, *t3f = nullptr, *uf = nullptr, *zf = nullptr;
   template <typename T> T* tmp(int i);
   double* part = nullptr;
+  // Gram-Schmidt partials left for the next update pass to sum (no finalize
+  // launch in between; grids of at most HANDOFF_MAXG workgroups), or null
+  const double* pend_part = nullptr;
+  int pend_G = 0;
   double* stats_buf = nullptr;   // 3 + 3*256 doubles for the setup statistics
   KState *ks = nullptr, *ksi = nullptr;
   double* hstat = nullptr;      // mapped pinned host memory
@@ -1384,11 +1388,19 @@ static int red_grid(long N, long per) {
 }
 
 static void finalize(fde_plan pl, int G, int nq, KState* ks, int fkind, int emode, int col, double* hstat,
-                     hipStream_t st, const int* skip, const int* skip2) {
+                     hipStream_t st, const int* skip, const int* skip2, const double* part = nullptr) {
   if (G <= 1) return;
-  hipLaunchKernelGGL(finalize_kernel, dim3(fkind == FK_H ? nq : 1), dim3(RED_THREADS), 0, st, pl->part, G, nq, ks,
-                     fkind, emode, col, hstat, skip, skip2);
+  hipLaunchKernelGGL(finalize_kernel, dim3(fkind == FK_H ? nq : 1), dim3(RED_THREADS), 0, st,
+                     part ? part : pl->part, G, nq, ks, fkind, emode, col, hstat, skip, skip2);
 }
+
+// A Gram-Schmidt pass with a grid of at most HANDOFF_MAXG workgroups leaves
+// its k coefficient partials to the update pass that follows it, whose
+// workgroups each sum them (k * G <= 32 * HANDOFF_MAXG values from L2) in
+// place of a finalize launch; the passes alternate between two regions of
+// the partials buffer so that a pass never overwrites what it reads.
+constexpr int HANDOFF_MAXG = 8 * HANDOFF_PER_THREAD;
+constexpr size_t PART_B = (size_t)HANDOFF_MAXG * 32;   // offset of the second region
 
 // ||a - b||^2 with an epilogue; out = a - b when out != null.
 template <typename T>
@@ -1409,13 +1421,24 @@ static void cgs_launch(fde_plan pl, const T* V, int k, T* w, KState* ks, int emo
   const int cls = sizeof(T) == 8 ? (MODE == CG_DOT ? FDE_PROBE_MDOT64 : FDE_PROBE_MAXPY64)
                                  : (MODE == CG_DOT ? FDE_PROBE_MDOT32 : FDE_PROBE_MAXPY32);
   const double bytes = (double)(k + (MODE == CG_DOT ? 1 : 2)) * N * sizeof(T);
+  // partials of the previous pass (update passes only), and where this pass writes its own
+  const double* pin = MODE != CG_DOT ? pl->pend_part : nullptr;
+  const int gin = pin ? pl->pend_G : 0;
+  pl->pend_part = nullptr;
+  double* pout = pin == pl->part ? pl->part + PART_B : pl->part;
   {
     ProbeScope ps(pl, cls, st, bytes, sizeof(T) == 8 ? FDE_PROBE_CGS64 : FDE_PROBE_CGS32);
     hipLaunchKernelGGL((cgs_kernel<T, KC, EPI, MODE>), dim3(G), dim3(RED_THREADS), 0, st, V, pl->ld, k, w, w, N, emode,
-                       col, pl->part, ks, hstat, skip, skip2);
+                       col, pout, ks, hstat, pin, gin, skip, skip2);
   }
-  if (MODE == CG_AXPY_NORM) finalize(pl, G, 1, ks, FK_NORM, emode, col, hstat, st, skip, skip2);
-  else finalize(pl, G, k, ks, FK_H, MODE == CG_AXPY_DOT ? EP_H2 : emode, col, hstat, st, skip, skip2);
+  if (MODE == CG_AXPY_NORM) {
+    finalize(pl, G, 1, ks, FK_NORM, emode, col, hstat, st, skip, skip2, pout);
+  } else if (G > 1 && G <= HANDOFF_MAXG) {
+    pl->pend_part = pout;   // summed by the next update pass
+    pl->pend_G = G;
+  } else {
+    finalize(pl, G, k, ks, FK_H, MODE == CG_AXPY_DOT ? EP_H2 : emode, col, hstat, st, skip, skip2, pout);
+  }
 }
 
 template <typename T, int MODE>
@@ -1582,6 +1605,7 @@ static fde_status trace_cycle(fde_plan pl, const Trace& tr, double beta0, int it
 static fde_status solve_gmres(fde_plan pl, const double* b, double* x, fde_info* info, hipStream_t st) {
   const long N = pl->N;
   KState* ks = pl->ks;
+  pl->pend_part = nullptr;
   hipLaunchKernelGGL(ks_init_kernel, dim3(1), dim3(1), 0, st, ks, pl->p.maxit, pl->m, pl->p.tol);
   hipLaunchKernelGGL(ks_init_kernel, dim3(1), dim3(1), 0, st, pl->ksi, 1 << 30, std::max(1, pl->kin), 0.0);
   norm_red<double>(pl, b, nullptr, nullptr, ks, EP_BNORM, st);

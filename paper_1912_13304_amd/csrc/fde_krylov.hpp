@@ -275,12 +275,58 @@ finalize_kernel(const double* part, int G, int /*nq: the grid for FK_H*/, KState
 //   CG_DOT       h_q = scale[q] <V_q, w>                     -> ks->h1 (emode EP_H1) or h2
 //   CG_AXPY_DOT  out = w - sum_q scale[q] h1[q] V_q,  h2_q = scale[q] <V_q, out>
 //   CG_AXPY_NORM out = w - sum_q scale[q] h2[q] V_q,  ||out|| -> Givens column `col`
+// An update pass takes its coefficients from the Krylov state, or, with
+// pin != null, from the gin workgroup partials the previous pass left
+// (that pass then had no finalize launch): see coef_from_parts.
 enum : int { CG_DOT = 0, CG_AXPY_DOT = 1, CG_AXPY_NORM = 2 };
+
+// A value that is the same in every lane, moved to scalar registers.
+__device__ __forceinline__ double uniform_value(double v) {
+  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+// Update coefficients c_q = scale[q] h_q, h_q = scale[q] sum_b pin[q gin + b],
+// summed by every workgroup of the update pass in the same fixed order (the
+// 8 threads of value q take b = r, r + 8, ... and a xor butterfly adds their
+// sums; the addends are the same in every lane, so every lane and every
+// workgroup gets the same value).  Workgroup 0 stores h_q and c_q in the
+// state as the finalize would (h1/c1 or h2/c2).  For KC <= 32 with 256
+// threads; the result goes to shc[0..k) in LDS.
+constexpr int HANDOFF_PER_THREAD = 16;   // partials per thread: grids of at most 8 * 16 = 128 workgroups
+__device__ inline void coef_from_parts(const double* pin, int gin, int k, KState* ks, bool second, double* shc) {
+  const int t = threadIdx.x, q = t >> 3, r = t & 7;
+  // all loads first (one memory latency), then the sum in order b = r, r + 8, ...
+  double v[HANDOFF_PER_THREAD];
+#pragma unroll
+  for (int i = 0; i < HANDOFF_PER_THREAD; ++i) {
+    const int b = r + 8 * i;
+    v[i] = (q < k && b < gin) ? pin[(size_t)q * gin + b] : 0.0;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < HANDOFF_PER_THREAD; ++i) s += v[i];
+  s += __shfl_xor(s, 1, 64);
+  s += __shfl_xor(s, 2, 64);
+  s += __shfl_xor(s, 4, 64);
+  if (q < k && r == 0) {
+    const double sq = ks->scale[q];
+    const double h = sq * s;
+    shc[q] = sq * h;
+    if (blockIdx.x == 0) {
+      (second ? ks->h2 : ks->h1)[q] = h;
+      (second ? ks->c2 : ks->c1)[q] = sq * h;
+    }
+  }
+  __syncthreads();
+}
 
 template <typename T, int KC, int EPI, int MODE>
 __global__ void __launch_bounds__(RED_THREADS)
 cgs_kernel(const T* __restrict__ V, long ldv, int k, const T* w, T* out, long N, int emode, int col,
-           double* part, KState* ks, double* hstat, const int* skip, const int* skip2) {
+           double* part, KState* ks, double* hstat, const double* pin, int gin, const int* skip,
+           const int* skip2) {
   if (skipped(skip, skip2)) return;
   // float32 elements are taken in aligned pairs (8-byte loads, ldv even), so
   // that every lane moves as many bytes per load as in the float64 kernel
@@ -291,8 +337,16 @@ cgs_kernel(const T* __restrict__ V, long ldv, int k, const T* w, T* out, long N,
   double coef[KC];   // uniform: kept in scalar registers
   if (MODE != CG_DOT) {
     const double* c = MODE == CG_AXPY_DOT ? ks->c1 : ks->c2;
+    if (pin) {
+      // (tot is written again only after the barrier inside the final
+      // reduction, which every wave reaches after reading its coefficients)
+      coef_from_parts(pin, gin, k, ks, MODE == CG_AXPY_NORM, tot);
 #pragma unroll
-    for (int q = 0; q < KC; ++q) coef[q] = q < k ? c[q] : 0.0;
+      for (int q = 0; q < KC; ++q) coef[q] = q < k ? uniform_value(tot[q]) : 0.0;
+    } else {
+#pragma unroll
+      for (int q = 0; q < KC; ++q) coef[q] = q < k ? c[q] : 0.0;
+    }
   }
   double acc[NA];
 #pragma unroll
