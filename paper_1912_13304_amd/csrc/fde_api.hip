@@ -104,6 +104,12 @@ struct fde_plan_s {
   // launch in between; grids of at most HANDOFF_MAXG workgroups), or null
   const double* pend_part = nullptr;
   int pend_G = 0;
+  // Toeplitz extraction of a long 1D line left to the first Gram-Schmidt
+  // pass (CG_XDOT): set by big_toep while defer_x is on (the outer step's
+  // operator, whose result w that pass reads next)
+  bool defer_x = false, xpend = false;
+  XArgs xpa;
+  double* xout = nullptr;
   double* stats_buf = nullptr;   // 3 + 3*256 doubles for the setup statistics
   KState *ks = nullptr, *ksi = nullptr;
   double* hstat = nullptr;      // mapped pinned host memory
@@ -979,7 +985,7 @@ static int ew_grid(long N);
 // z = S F^{-1} S (pre .* sc v) .* post   (1D big line); z2: optional second copy
 template <typename T>
 static void big_tau(fde_plan pl, const T* v, const double* sc, const T* pre, const T* post, T* z, T* z2,
-                    hipStream_t st, const int* skip, const int* skip2) {
+                    hipStream_t st, const int* skip, const int* skip2, bool raw = false) {
   const Consts<T>& c = consts<T>(pl);
   const int P = pl->rows.P, n = pl->n1;
   if (pl->blue) {   // chirp-z DST, divide by F, chirp-z DST
@@ -999,13 +1005,17 @@ static void big_tau(fde_plan pl, const T* v, const double* sc, const T* pre, con
   const int g = ew_grid(P);
   big_fft<T>(pl, LdPackDst<T>{v, pre, sc, P}, c0, c1, 1, st, skip, skip2);
   big_fft<T>(pl, LdFRepack<T>{c0, c.W2x, c.fx, P}, c0, c1, 1, st, skip, skip2);
+  if (raw) return;   // the caller unpacks from c0 (LdDstPackToep)
   hipLaunchKernelGGL((unpack_dst_kernel<T>), dim3(g), dim3(256), 0, st, c0, c.W2x, post, z, z2, n, P, skip, skip2);
 }
 
-// out = bscale * base + tscale * (D+ T x + D- T^T x)   (1D big line)
-template <typename T>
-static void big_toep(fde_plan pl, const T* x, const T* base, T bscale, T tscale, T* out, hipStream_t st,
-                     const int* skip, const int* skip2) {
+// out = bscale * base + tscale * (D+ T x + D- T^T x)   (1D big line); the
+// loader supplies the packed x (LdPackToep, or LdDstPackToep straight from
+// the preconditioner's last FFT).  With defer_x (float64) the extraction is
+// left to the first Gram-Schmidt pass of the outer step.
+template <typename T, class LD>
+static void big_toep_ld(fde_plan pl, LD ld, const T* base, T bscale, T tscale, T* out, hipStream_t st,
+                        const int* skip, const int* skip2) {
   const Consts<T>& c = consts<T>(pl);
   const int P = pl->rows.P, n = pl->n1;
   cx<T>* c0 = c.cw;
@@ -1013,10 +1023,25 @@ static void big_toep(fde_plan pl, const T* x, const T* base, T bscale, T tscale,
   cx<T>* c2 = c.cw + 2 * P;
   cx<T>* c3 = c.cw + 4 * P;
   const int g = ew_grid(P);
-  big_fft<T>(pl, LdPackToep<T>{x, n}, c0, c1, 1, st, skip, skip2);
+  big_fft<T>(pl, ld, c0, c1, 1, st, skip, skip2);
   big_fft<T>(pl, LdPairToep<T>{c0, c.lamx, c.W2x, P}, c3, c2, 2, st, skip, skip2);
+  if constexpr (sizeof(T) == 8) {
+    if (pl->defer_x) {
+      pl->xpa = XArgs{reinterpret_cast<const double*>(c3), reinterpret_cast<const double*>(c3 + P), c.dp, c.dm,
+                      base, bscale, tscale, P};
+      pl->xout = out;
+      pl->xpend = true;
+      return;
+    }
+  }
   hipLaunchKernelGGL((extract_toep_kernel<T>), dim3(g), dim3(256), 0, st, c3, c3 + P, c.dp, c.dm, base, bscale, tscale,
                      out, n, P, skip, skip2);
+}
+
+template <typename T>
+static void big_toep(fde_plan pl, const T* x, const T* base, T bscale, T tscale, T* out, hipStream_t st,
+                     const int* skip, const int* skip2) {
+  big_toep_ld<T>(pl, LdPackToep<T>{x, pl->n1}, base, bscale, tscale, out, st, skip, skip2);
 }
 
 // z = P^{-1}(sc * v) (stored when z != null; the DST-side factors D^{-1} as
@@ -1171,6 +1196,13 @@ static void tau_matvec(fde_plan pl, const T* v, const double* sc, T* z, T* w, hi
   const T* post = (pl->has_dinv && pl->dside == FDE_D_RIGHT) ? c.dinv : nullptr;
   if (pl->dim == 1 && pl->big) {
     T* zz = z ? z : pl->tmp<T>(1);
+    if (tau && !pl->blue) {
+      // the second DST's unpacking is the Toeplitz product's packing loader
+      big_tau<T>(pl, v, sc, pre, post, zz, nullptr, st, skip, skip2, true);
+      big_toep_ld<T>(pl, LdDstPackToep<T>{c.cw, c.W2x, post, zz, pl->n1, pl->rows.P}, zz, (T)pl->nu, T(1), w, st,
+                     skip, skip2);
+      return;
+    }
     if (tau) {
       big_tau<T>(pl, v, sc, pre, post, zz, nullptr, st, skip, skip2);
     } else {
@@ -1418,18 +1450,20 @@ static void cgs_launch(fde_plan pl, const T* V, int k, T* w, KState* ks, int emo
   const long N = pl->N;
   // float32 kernels take element pairs: the same grid as float64 covers them in one pass
   const int G = red_grid(N, (long)RED_THREADS * EPI * 2);
-  const int cls = sizeof(T) == 8 ? (MODE == CG_DOT ? FDE_PROBE_MDOT64 : FDE_PROBE_MAXPY64)
-                                 : (MODE == CG_DOT ? FDE_PROBE_MDOT32 : FDE_PROBE_MAXPY32);
-  const double bytes = (double)(k + (MODE == CG_DOT ? 1 : 2)) * N * sizeof(T);
+  constexpr bool DOT = MODE == CG_DOT || MODE == CG_XDOT;
+  const int cls = sizeof(T) == 8 ? (DOT ? FDE_PROBE_MDOT64 : FDE_PROBE_MAXPY64)
+                                 : (DOT ? FDE_PROBE_MDOT32 : FDE_PROBE_MAXPY32);
+  // (the extraction pass also reads the two FFT lines, base and d+-, and writes w)
+  const double bytes = (double)(k + (DOT ? 1 : 2) + (MODE == CG_XDOT ? 7 : 0)) * N * sizeof(T);
   // partials of the previous pass (update passes only), and where this pass writes its own
-  const double* pin = MODE != CG_DOT ? pl->pend_part : nullptr;
+  const double* pin = !DOT ? pl->pend_part : nullptr;
   const int gin = pin ? pl->pend_G : 0;
   pl->pend_part = nullptr;
   double* pout = pin == pl->part ? pl->part + PART_B : pl->part;
   {
     ProbeScope ps(pl, cls, st, bytes, sizeof(T) == 8 ? FDE_PROBE_CGS64 : FDE_PROBE_CGS32);
     hipLaunchKernelGGL((cgs_kernel<T, KC, EPI, MODE>), dim3(G), dim3(RED_THREADS), 0, st, V, pl->ld, k, w, w, N, emode,
-                       col, pout, ks, hstat, pin, gin, skip, skip2);
+                       col, pout, ks, hstat, pin, gin, MODE == CG_XDOT ? pl->xpa : XArgs{}, skip, skip2);
   }
   if (MODE == CG_AXPY_NORM) {
     finalize(pl, G, 1, ks, FK_NORM, emode, col, hstat, st, skip, skip2, pout);
@@ -1442,13 +1476,32 @@ static void cgs_launch(fde_plan pl, const T* V, int k, T* w, KState* ks, int emo
 }
 
 template <typename T, int MODE>
-static void cgs_pass(fde_plan pl, const T* V, int k, T* w, KState* ks, int emode, int col, double* hstat,
-                     hipStream_t st, const int* skip, const int* skip2) {
+static void cgs_pass_k(fde_plan pl, const T* V, int k, T* w, KState* ks, int emode, int col, double* hstat,
+                       hipStream_t st, const int* skip, const int* skip2) {
   // (twice the elements per thread for float32 was measured slower: fewer workgroups)
   constexpr int X = 1;
   if (k <= 8) cgs_launch<T, 8, 4 * X, MODE>(pl, V, k, w, ks, emode, col, hstat, st, skip, skip2);
   else if (k <= 16) cgs_launch<T, 16, 2 * X, MODE>(pl, V, k, w, ks, emode, col, hstat, st, skip, skip2);
   else cgs_launch<T, 32, 1 * X, MODE>(pl, V, k, w, ks, emode, col, hstat, st, skip, skip2);
+}
+
+template <typename T, int MODE>
+static void cgs_pass(fde_plan pl, const T* V, int k, T* w, KState* ks, int emode, int col, double* hstat,
+                     hipStream_t st, const int* skip, const int* skip2) {
+  if constexpr (MODE == CG_DOT && sizeof(T) == 8) {
+    if (pl->xpend) {   // w still to be extracted from the Toeplitz product's FFT lines
+      pl->xpend = false;
+      if (pl->xout == w) {
+        cgs_pass_k<double, CG_XDOT>(pl, V, k, w, ks, emode, col, hstat, st, skip, skip2);
+        return;
+      }
+      const XArgs& a = pl->xpa;
+      hipLaunchKernelGGL((extract_toep_kernel<double>), dim3(ew_grid(pl->rows.P)), dim3(256), 0, st,
+                         reinterpret_cast<const cx<double>*>(a.r1), reinterpret_cast<const cx<double>*>(a.r2), a.cp,
+                         a.cm, a.base, a.bscale, a.tscale, pl->xout, pl->n1, a.P, skip, skip2);
+    }
+  }
+  cgs_pass_k<T, MODE>(pl, V, k, w, ks, emode, col, hstat, st, skip, skip2);
 }
 
 // One classical Gram-Schmidt pass (h = V^T w into h2, then w -= V h and
@@ -1516,6 +1569,7 @@ static void outer_step(fde_plan pl, int j, hipStream_t st) {
   double* vj = pl->V + (long)j * ld;
   double* w = pl->V + (long)(j + 1) * ld;
   double* zj = pl->Z + (long)j * ld;
+  pl->defer_x = pl->dim == 1 && pl->big;   // the CGS2 below starts with w
   if (pl->p.precision == FDE_FP64) {
     tau_matvec<double>(pl, vj, &ks->scale[j], zj, w, st, skip, nullptr);
   } else {
@@ -1532,6 +1586,7 @@ static void outer_step(fde_plan pl, int j, hipStream_t st) {
                        nullptr, skip, nullptr);
     matvec_only<double>(pl, zj, w, pl->nu, 1.0, st, skip);
   }
+  pl->defer_x = false;
   cgs2_givens<double>(pl, pl->V, w, j, ks, pl->hstat_dev, st, skip, nullptr);
 }
 

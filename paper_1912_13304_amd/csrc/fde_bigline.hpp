@@ -181,6 +181,27 @@ struct LdPackToep {
   }
 };
 
+// The preconditioner's last step and the Toeplitz packing in one loader: the
+// DST values y_{m+1} (times post_m) from the FFT Z of the second DST, written
+// to zout (the stored z = P^{-1} v) and packed as LdPackToep packs them.
+// Every index j is loaded once per pass, so each z_m is written once.
+template <typename T>
+struct LdDstPackToep {
+  const cx<T>* Z;
+  const cx<T>* W;
+  const T* post;
+  T* zout;
+  int n, P;
+  __device__ T zval(long m) const {
+    if (m >= n) return T(0);
+    T y = dst_value(Z, W, (int)m + 1, P);
+    if (post) y *= post[m];
+    zout[m] = y;
+    return y;
+  }
+  __device__ cx<T> operator()(long, long j) const { return mk(zval(2 * j), zval(2 * j + 1)); }
+};
+
 // Pair phase of the Toeplitz product: from Q (FFT of the packed zero-padded
 // input) the half spectrum Ph, Y1 = lam Ph (item 0) or Y2 = conj(lam) Ph
 // (item 1), and bin k of the conjugated packed inverse input conj(W1) or

@@ -278,7 +278,22 @@ finalize_kernel(const double* part, int G, int /*nq: the grid for FK_H*/, KState
 // An update pass takes its coefficients from the Krylov state, or, with
 // pin != null, from the gin workgroup partials the previous pass left
 // (that pass then had no finalize launch): see coef_from_parts.
-enum : int { CG_DOT = 0, CG_AXPY_DOT = 1, CG_AXPY_NORM = 2 };
+//   CG_XDOT      CG_DOT of w = bscale base + tscale (cp y1 + cm y2), the
+//                Toeplitz pair extraction of a long 1D line (y1, y2 entry m of
+//                the two inverse FFTs R1, R2: Re or -Im of R[m/2], over P),
+//                computed here and stored to out (float64 only)
+enum : int { CG_DOT = 0, CG_AXPY_DOT = 1, CG_AXPY_NORM = 2, CG_XDOT = 3 };
+
+// Operands of the CG_XDOT extraction (R1, R2 as interleaved re/im pairs).
+struct XArgs {
+  const double* r1 = nullptr;
+  const double* r2 = nullptr;
+  const double* cp = nullptr;
+  const double* cm = nullptr;
+  const double* base = nullptr;
+  double bscale = 0.0, tscale = 0.0;
+  int P = 1;
+};
 
 // A value that is the same in every lane, moved to scalar registers.
 __device__ __forceinline__ double uniform_value(double v) {
@@ -325,9 +340,11 @@ __device__ inline void coef_from_parts(const double* pin, int gin, int k, KState
 template <typename T, int KC, int EPI, int MODE>
 __global__ void __launch_bounds__(RED_THREADS)
 cgs_kernel(const T* __restrict__ V, long ldv, int k, const T* w, T* out, long N, int emode, int col,
-           double* part, KState* ks, double* hstat, const double* pin, int gin, const int* skip,
+           double* part, KState* ks, double* hstat, const double* pin, int gin, XArgs xa, const int* skip,
            const int* skip2) {
   if (skipped(skip, skip2)) return;
+  static_assert(MODE != CG_XDOT || sizeof(T) == 8, "the extraction pass is float64");
+  constexpr bool DOT = MODE == CG_DOT || MODE == CG_XDOT;
   // float32 elements are taken in aligned pairs (8-byte loads, ldv even), so
   // that every lane moves as many bytes per load as in the float64 kernel
   constexpr int VW = sizeof(T) == 4 ? 2 : 1;
@@ -335,7 +352,7 @@ cgs_kernel(const T* __restrict__ V, long ldv, int k, const T* w, T* out, long N,
   __shared__ double red[16 * NA];
   __shared__ double tot[NA > KMAX + 1 ? NA : KMAX + 1];
   double coef[KC];   // uniform: kept in scalar registers
-  if (MODE != CG_DOT) {
+  if (!DOT) {
     const double* c = MODE == CG_AXPY_DOT ? ks->c1 : ks->c2;
     if (pin) {
       // (tot is written again only after the barrier inside the final
@@ -380,12 +397,25 @@ cgs_kernel(const T* __restrict__ V, long ldv, int k, const T* w, T* out, long N,
       }
 #pragma unroll
       for (int v = 0; v < VW; ++v) {
-        x[i][v] = ok[i][v] ? (double)w[e + v] : 0.0;
+        if constexpr (MODE == CG_XDOT) {
+          double xv = 0.0;
+          if (ok[i][v]) {
+            const long m = e + v, h = 2 * (m >> 1) + (m & 1);
+            const double invP = 1.0 / (double)xa.P;
+            const double y1 = ((m & 1) ? -xa.r1[h] : xa.r1[h]) * invP;
+            const double y2 = ((m & 1) ? -xa.r2[h] : xa.r2[h]) * invP;
+            xv = xa.bscale * xa.base[m] + xa.tscale * (xa.cp[m] * y1 + xa.cm[m] * y2);
+            out[m] = (T)xv;
+          }
+          x[i][v] = xv;
+        } else {
+          x[i][v] = ok[i][v] ? (double)w[e + v] : 0.0;
+        }
 #pragma unroll
         for (int q = 0; q < KC; ++q) vq[i][q][v] = (ok[i][v] && q < k) ? V[(long)q * ldv + e + v] : T(0);
       }
     }
-    if (MODE != CG_DOT) {
+    if (!DOT) {
 #pragma unroll
       for (int i = 0; i < EPI; ++i) {
         T r[VW];
