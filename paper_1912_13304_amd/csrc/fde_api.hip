@@ -996,6 +996,7 @@ static void big_tau(fde_plan pl, const T* v, const double* sc, const T* pre, con
     big_fft<T>(pl, LdChirpMul<T>{a0, c.bhat}, a0, a1, 1, st, skip, skip2, true);
     big_fft<T>(pl, LdChirpMid<T>{a0, c.chirp, c.fx, n}, a0, a1, 1, st, skip, skip2, true);
     big_fft<T>(pl, LdChirpMul<T>{a0, c.bhat}, a0, a1, 1, st, skip, skip2, true);
+    if (raw) return;   // the caller unpacks from a0 (LdChirpPackToep)
     hipLaunchKernelGGL((unpack_chirp_kernel<T>), dim3(ew_grid(n)), dim3(256), 0, st, a0, c.chirp, post, z, z2, n,
                        skip, skip2);
     return;
@@ -1196,19 +1197,21 @@ static void tau_matvec(fde_plan pl, const T* v, const double* sc, T* z, T* w, hi
   const T* post = (pl->has_dinv && pl->dside == FDE_D_RIGHT) ? c.dinv : nullptr;
   if (pl->dim == 1 && pl->big) {
     T* zz = z ? z : pl->tmp<T>(1);
-    if (tau && !pl->blue) {
+    if (tau) {
       // the second DST's unpacking is the Toeplitz product's packing loader
+      // (the DST's output occupies c.cw below the Toeplitz FFT's scratch,
+      // which starts at c.cw + P, P > n)
       big_tau<T>(pl, v, sc, pre, post, zz, nullptr, st, skip, skip2, true);
-      big_toep_ld<T>(pl, LdDstPackToep<T>{c.cw, c.W2x, post, zz, pl->n1, pl->rows.P}, zz, (T)pl->nu, T(1), w, st,
-                     skip, skip2);
+      if (pl->blue)
+        big_toep_ld<T>(pl, LdChirpPackToep<T>{c.cw, c.chirp, post, zz, pl->n1}, zz, (T)pl->nu, T(1), w, st, skip,
+                       skip2);
+      else
+        big_toep_ld<T>(pl, LdDstPackToep<T>{c.cw, c.W2x, post, zz, pl->n1, pl->rows.P}, zz, (T)pl->nu, T(1), w, st,
+                       skip, skip2);
       return;
     }
-    if (tau) {
-      big_tau<T>(pl, v, sc, pre, post, zz, nullptr, st, skip, skip2);
-    } else {
-      hipLaunchKernelGGL((scale_cast_kernel<T, T>), dim3(ew_grid(pl->N)), dim3(256), 0, st, v, zz, pl->N, sc, skip,
-                         skip2);
-    }
+    hipLaunchKernelGGL((scale_cast_kernel<T, T>), dim3(ew_grid(pl->N)), dim3(256), 0, st, v, zz, pl->N, sc, skip,
+                       skip2);
     big_toep<T>(pl, zz, zz, (T)pl->nu, T(1), w, st, skip, skip2);
     return;
   }

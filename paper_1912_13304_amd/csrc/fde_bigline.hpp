@@ -313,6 +313,26 @@ __global__ void unpack_chirp_kernel(const cx<T>* R, const cx<T>* chirp, const T*
   }
 }
 
+// The chirp-z preconditioner's last step and the Toeplitz packing in one
+// loader (as LdDstPackToep): y_{m+1} (times post_m) from the second FFT's
+// output R, written to zout and packed.
+template <typename T>
+struct LdChirpPackToep {
+  const cx<T>* R;
+  const cx<T>* chirp;
+  const T* post;
+  T* zout;
+  int n;
+  __device__ T zval(long m) const {
+    if (m >= n) return T(0);
+    T y = chirp_value(R, chirp, m);
+    if (post) y *= post[m];
+    zout[m] = y;
+    return y;
+  }
+  __device__ cx<T> operator()(long, long j) const { return mk(zval(2 * j), zval(2 * j + 1)); }
+};
+
 // out_m = bscale * base_m + tscale * (cplus_m y1_m + cminus_m y2_m), where
 // y_{2j} = Re R_j / P and y_{2j+1} = -Im R_j / P for R = FFT(conj W).
 template <typename T>
