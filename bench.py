@@ -407,7 +407,7 @@ def one_d_legs(args, fi, fde, torch, np):
     log(f"[bench] 1D PCG: {out['pcg_constant_1023']}")
     jobs = {}
     for alpha in (1.2, 1.5, 1.8):
-        p = fi.variable_1d(n=65535, alpha=alpha, steps=20)
+        p = fi.variable_1d(n=65535, alpha=alpha, steps=args.oned_steps if args else 20)
         for name, kw in (("fp64", dict(precision=fde.FP64)), ("mixed", dict(precision=fde.MIXED, inner_steps=0))):
             with fde.Plan(p, **kw) as plan:
                 u = T(p.u0)
@@ -464,6 +464,9 @@ def main():
     ap.add_argument("--acc-tol", type=float, default=1e-9,
                     help="outer tolerance of the accuracy-matched forms (forward error <= 1e-8 against the "
                          "oracle's reference solution)")
+    ap.add_argument("--only-1d", action="store_true",
+                    help="only the 1D legs (PCG time-to-tol and the n = 65535 jobs), one JSON line")
+    ap.add_argument("--oned-steps", type=int, default=20, help="implicit steps of each n = 65535 job")
     ap.add_argument("--only-pcg", action="store_true",
                     help="run the 1D constant-coefficient PCG leg alone (profiling); prints its JSON object")
     ap.add_argument("--table", choices=["variants", "paper2d", "dense"], default=None,
@@ -492,6 +495,9 @@ def main():
         return
     if args.only_pcg:
         print(json.dumps({"pcg_constant_1023": pcg_leg(fi, fde, torch, np, solves=50)}), flush=True)
+        return
+    if args.only_1d:
+        print(json.dumps({"one_d": one_d_legs(args, fi, fde, torch, np)}), flush=True)
         return
     if args.table == "variants":
         print(json.dumps({"table": "variants", "rows": table_variants(fi, fde, torch, np)}), flush=True)
