@@ -655,3 +655,29 @@ def test_dense_size_limits():
         with pytest.raises(fde.FdeError) as e:
             fde.Plan(prob2d(n1, n2))
         assert e.value.status == fde.FDE_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("n,alpha,restart", [(7, 1.5, 30), (255, 1.3, 30), (1023, 1.6, 5), (1023, 1.2, 30)])
+def test_fgmres_one_workgroup_matches_multikernel(tmp_path, n, alpha, restart):
+    """1D FGMRES with n + 1 <= 1024 runs in one workgroup; a traced solve
+    (FDE_TRACE set) takes the multi-kernel path.  Both start from the same
+    x0 and follow the same steps: iteration counts within one, solutions
+    within 1e-10, and each mirrors the oracle."""
+    import os
+    fde = need_gpu()
+    p = fi.variable_1d(n=n, alpha=alpha, seed=n + 3, steps=1)
+    s = FDESystem.from_problem(p)
+    b = s.rhs(p.u0)
+    xa, ia = gpu_solve(fde, p, b, p.u0, restart=restart)
+    os.environ["FDE_TRACE"] = str(tmp_path / "trace.txt")
+    try:
+        xb, ib = gpu_solve(fde, p, b, p.u0, restart=restart)
+    finally:
+        del os.environ["FDE_TRACE"]
+    assert (tmp_path / "trace.txt").exists()   # the traced solve did take the multi-kernel path
+    assert ia.converged and ib.converged
+    assert abs(ia.iters - ib.iters) <= 1, (ia.iters, ib.iters)
+    assert relerr(s.matvec(xa), b) <= 1e-8 * (1 + 1e-6)
+    if ia.iters == ib.iters:
+        assert relerr(xa, xb) < 1e-10
+    mirror(fde, p, b, p.u0, xa, ia, restart=restart)
