@@ -984,8 +984,8 @@ static void big_fft(fde_plan pl, LD ld, cx<T>* out, cx<T>* tmp, int batch, hipSt
 static int ew_grid(long N);
 
 // z = S F^{-1} S (pre .* sc v) .* post   (1D big line); z2: optional second copy
-template <typename T>
-static void big_tau(fde_plan pl, const T* v, const double* sc, const T* pre, const T* post, T* z, T* z2,
+template <typename T, typename TI = T>
+static void big_tau(fde_plan pl, const TI* v, const double* sc, const T* pre, const T* post, T* z, T* z2,
                     hipStream_t st, const int* skip, const int* skip2, bool raw = false) {
   const Consts<T>& c = consts<T>(pl);
   const int P = pl->rows.P, n = pl->n1;
@@ -993,7 +993,7 @@ static void big_tau(fde_plan pl, const T* v, const double* sc, const T* pre, con
     const long Q = pl->sQ;
     cx<T>* a0 = c.cw;
     cx<T>* a1 = c.cw + Q;
-    big_fft<T>(pl, LdChirpIn<T>{v, pre, sc, c.chirp, n}, a0, a1, 1, st, skip, skip2, true);
+    big_fft<T>(pl, LdChirpIn<T, TI>{v, pre, sc, c.chirp, n}, a0, a1, 1, st, skip, skip2, true);
     big_fft<T>(pl, LdChirpMul<T>{a0, c.bhat}, a0, a1, 1, st, skip, skip2, true);
     big_fft<T>(pl, LdChirpMid<T>{a0, c.chirp, c.fx, n}, a0, a1, 1, st, skip, skip2, true);
     big_fft<T>(pl, LdChirpMul<T>{a0, c.bhat}, a0, a1, 1, st, skip, skip2, true);
@@ -1005,7 +1005,7 @@ static void big_tau(fde_plan pl, const T* v, const double* sc, const T* pre, con
   cx<T>* c0 = c.cw;
   cx<T>* c1 = c.cw + P;
   const int g = ew_grid(P);
-  big_fft<T>(pl, LdPackDst<T>{v, pre, sc, P}, c0, c1, 1, st, skip, skip2);
+  big_fft<T>(pl, LdPackDst<T, TI>{v, pre, sc, P}, c0, c1, 1, st, skip, skip2);
   big_fft<T>(pl, LdFRepack<T>{c0, c.W2x, c.fx, P}, c0, c1, 1, st, skip, skip2);
   if (raw) return;   // the caller unpacks from c0 (LdDstPackToep)
   hipLaunchKernelGGL((unpack_dst_kernel<T>), dim3(g), dim3(256), 0, st, c0, c.W2x, post, z, z2, n, P, skip, skip2);
@@ -1576,6 +1576,19 @@ static void outer_step(fde_plan pl, int j, hipStream_t st) {
   pl->defer_x = pl->dim == 1 && pl->big;   // the CGS2 below starts with w
   if (pl->p.precision == FDE_FP64) {
     tau_matvec<double>(pl, vj, &ks->scale[j], zj, w, st, skip, nullptr);
+  } else if (pl->kin == 0 && pl->dim == 1 && pl->big && pl->p.prec != FDE_P_NONE && pl->p.prec != FDE_P_TRI) {
+    // long 1D line, float32 P^{-1} alone: its first loader scales and casts
+    // v_j, and the Toeplitz product's loader casts its result (stored as z_j)
+    const Consts<float>& c = pl->c32;
+    const float* pre = (pl->has_dinv && pl->dside == FDE_D_LEFT) ? c.dinv : nullptr;
+    const float* post = (pl->has_dinv && pl->dside == FDE_D_RIGHT) ? c.dinv : nullptr;
+    big_tau<float, double>(pl, vj, &ks->scale[j], pre, post, nullptr, nullptr, st, skip, nullptr, true);
+    if (pl->blue)
+      big_toep_ld<double>(pl, LdChirpPackToep<double, float>{c.cw, c.chirp, post, zj, pl->n1}, zj, pl->nu, 1.0, w,
+                          st, skip, nullptr);
+    else
+      big_toep_ld<double>(pl, LdDstPackToep<double, float>{c.cw, c.W2x, post, zj, pl->n1, pl->rows.P}, zj, pl->nu,
+                          1.0, w, st, skip, nullptr);
   } else {
     if (pl->kin == 0) {
       hipLaunchKernelGGL((scale_cast_kernel<double, float>), dim3(ew_grid(N)), dim3(256), 0, st, vj, pl->uf, N,

@@ -113,21 +113,26 @@ struct LdArray {
 
 // DST packing: z_j = u_{2j} + i u_{2j+1}, u the odd extension (length 2P) of
 // x_m = sc * pre_m * in_{m-1}, m = 1..n (u_0 = u_P = 0, u_{2P-m} = -x_m).
-template <typename T>
+// The input may be of a wider type TI (a float64 vector into the float32
+// transform): then x_m = (T)(in_{m-1} sc) is formed in TI, as a separate
+// scale-and-cast kernel would.
+template <typename T, typename TI = T>
 struct LdPackDst {
-  const T* in;
+  const TI* in;
   const T* pre;
   const double* sc;
   int P;
-  __device__ T u(int m, T s) const {
+  __device__ T u(int m, double s) const {
     if (m == 0 || m == P) return T(0);
     const int mm = m < P ? m : 2 * P - m;
-    T x = in[mm - 1] * s;
+    T x;
+    if constexpr (sizeof(TI) == sizeof(T)) x = in[mm - 1] * (T)s;
+    else x = (T)((double)in[mm - 1] * s);
     if (pre) x *= pre[mm - 1];
     return m < P ? x : -x;
   }
   __device__ cx<T> operator()(long, long j) const {
-    const T s = sc ? (T)(*sc) : T(1);
+    const double s = sc ? *sc : 1.0;
     return mk(u(2 * (int)j, s), u(2 * (int)j + 1, s));
   }
 };
@@ -185,19 +190,22 @@ struct LdPackToep {
 // DST values y_{m+1} (times post_m) from the FFT Z of the second DST, written
 // to zout (the stored z = P^{-1} v) and packed as LdPackToep packs them.
 // Every index j is loaded once per pass, so each z_m is written once.
-template <typename T>
+// TZ: the preconditioner's precision (float32 in the mixed form, whose z
+// is stored and multiplied in float64: y is then rounded once, to T).
+template <typename T, typename TZ = T>
 struct LdDstPackToep {
-  const cx<T>* Z;
-  const cx<T>* W;
-  const T* post;
+  const cx<TZ>* Z;
+  const cx<TZ>* W;
+  const TZ* post;
   T* zout;
   int n, P;
   __device__ T zval(long m) const {
     if (m >= n) return T(0);
-    T y = dst_value(Z, W, (int)m + 1, P);
+    TZ y = dst_value(Z, W, (int)m + 1, P);
     if (post) y *= post[m];
-    zout[m] = y;
-    return y;
+    const T yt = (T)y;
+    zout[m] = yt;
+    return yt;
   }
   __device__ cx<T> operator()(long, long j) const { return mk(zval(2 * j), zval(2 * j + 1)); }
 };
@@ -253,17 +261,22 @@ struct LdPairToep {
 // ---------------------------------------------------------------------------
 
 // First FFT input: a_j = sc pre_j in_j c_{j+1} (j < n), zero beyond.
-template <typename T>
+template <typename T, typename TI = T>
 struct LdChirpIn {
-  const T* in;
+  const TI* in;
   const T* pre;
   const double* sc;
   const cx<T>* chirp;
   int n;
   __device__ cx<T> operator()(long, long j) const {
     if (j >= n) return mk(T(0), T(0));
-    T u = in[j];
-    if (sc) u *= (T)(*sc);
+    T u;
+    if constexpr (sizeof(TI) == sizeof(T)) {
+      u = in[j];
+      if (sc) u *= (T)(*sc);
+    } else {
+      u = (T)((double)in[j] * (sc ? *sc : 1.0));
+    }
     if (pre) u *= pre[j];
     const cx<T> c = chirp[j + 1];
     return mk(u * c.x, u * c.y);
@@ -316,19 +329,20 @@ __global__ void unpack_chirp_kernel(const cx<T>* R, const cx<T>* chirp, const T*
 // The chirp-z preconditioner's last step and the Toeplitz packing in one
 // loader (as LdDstPackToep): y_{m+1} (times post_m) from the second FFT's
 // output R, written to zout and packed.
-template <typename T>
+template <typename T, typename TZ = T>
 struct LdChirpPackToep {
-  const cx<T>* R;
-  const cx<T>* chirp;
-  const T* post;
+  const cx<TZ>* R;
+  const cx<TZ>* chirp;
+  const TZ* post;
   T* zout;
   int n;
   __device__ T zval(long m) const {
     if (m >= n) return T(0);
-    T y = chirp_value(R, chirp, m);
+    TZ y = chirp_value(R, chirp, m);
     if (post) y *= post[m];
-    zout[m] = y;
-    return y;
+    const T yt = (T)y;
+    zout[m] = yt;
+    return yt;
   }
   __device__ cx<T> operator()(long, long j) const { return mk(zval(2 * j), zval(2 * j + 1)); }
 };
