@@ -225,7 +225,7 @@ def served_leg(args, fi, fde):
     log(f"[bench] served: {out}")
     res, _ = serve.serve_stream(arr, slots=slots, precision=serve.AUTO, inner_steps=args.inner)
     auto = serve.latency_stats(res, slots)
-    auto.update(policy="mixed for 2D requests, float64 for 1D requests")
+    auto.update(policy="mixed for 2D requests with n >= 511, float64 for smaller 2D and for 1D requests")
     out["per_request_precision"] = auto
     log(f"[bench] served, per-request precision: {auto}")
     log(f"[bench] served: the same stream one request at a time in float64")

@@ -62,21 +62,26 @@ class Result:
 AUTO = "auto"
 CANCELLED = -100   # Result.status of a cancelled request (a server status, not a library one)
 INNER_2D = 16   # float32 inner GMRES steps of a 2D mixed request
+MIXED_2D_MIN_N = 511   # smallest 2D grid side served in the mixed form under precision="auto"
 
 
 def request_kw(problem, solve_kw: dict) -> dict:
     """Solver options of one request, with the per-class choices measured on
     the benchmark's workloads:
-      precision="auto": the mixed form for 2D requests, where its float32
-        inner steps move half the bytes, and float64 for 1D requests, whose
-        long-line iterations are bound by kernel launches rather than bytes;
+      precision="auto": the mixed form for 2D requests from MIXED_2D_MIN_N
+        up, where its float32 inner steps move half the bytes (at 511^2 and
+        1023^2 about 10 % and 30 % faster than float64), and float64 for
+        smaller 2D grids (at 127^2 and 255^2 float64 is 10 % faster: their
+        launches, not their bytes, set the pace) and for 1D requests, whose
+        long-line iterations are launch-bound too and need fewer iterations
+        in float64;
       inner_steps="auto" (mixed requests): GMRES(INNER_2D) in float32 for 2D,
         and no inner steps (the float32 preconditioner alone inside the
         float64 FGMRES) for 1D, where the float32 inner iterations do not pay
         for themselves."""
     kw = dict(solve_kw)
     if kw.get("precision") == AUTO:
-        kw["precision"] = fde.MIXED if problem.dim == 2 else fde.FP64
+        kw["precision"] = fde.MIXED if problem.dim == 2 and min(problem.n) >= MIXED_2D_MIN_N else fde.FP64
     if kw.get("precision") != fde.MIXED:
         kw.pop("inner_steps", None)
     elif kw.get("inner_steps") == AUTO:
