@@ -414,6 +414,11 @@ def test_zero_rhs_and_nonfinite():
         with pytest.raises(fde.FdeError) as e:
             plan.solve(dev(b), dev(np.zeros(63)))
         assert e.value.status == fde.FDE_ENONFINITE
+        x0 = np.zeros(63)
+        x0[7] = np.inf   # a finite b, a non-finite start: the first residual is not finite
+        with pytest.raises(fde.FdeError) as e:
+            plan.solve(dev(np.ones(63)), dev(x0))
+        assert e.value.status == fde.FDE_ENONFINITE
 
 
 def test_maxit_returns_notconv_with_info():
