@@ -135,6 +135,14 @@ fde_status fde_matvec(fde_plan plan, const double* x, double* y, void* stream);
    v, z: device, length N. */
 fde_status fde_tau_apply(fde_plan plan, const double* v, double* z, void* stream);
 
+/* The same two operators in float32 arithmetic, the arithmetic of the mixed
+   form's inner solves: x (v) rounded to float32, the operator applied in
+   float32, the result widened into y (z).  The plan must have been assembled
+   with precision = FDE_MIXED (FDE_EINVAL otherwise).  Float64 device arrays of
+   length N; asynchronous on `stream`. */
+fde_status fde_matvec_f32(fde_plan plan, const double* x, double* y, void* stream);
+fde_status fde_tau_apply_f32(fde_plan plan, const double* v, double* z, void* stream);
+
 /* Solves M x = b (eq. linsystem).  b: device, length N.  x: device, length
    N, holds the starting vector on entry and the solution on return.  info:
    host pointer or NULL.  Synchronises `stream`.  b = 0 returns x = 0 with 0
@@ -251,8 +259,9 @@ fde_status fde_batch_solve(fde_batch batch, const double* b, double* x, fde_info
    solve).  precision = FDE_FP64 computes in float64; FDE_MIXED in float32
    (the arithmetic of the mixed form's inner solves; the batch must have been
    assembled with FDE_MIXED).  Inputs and outputs are float64 and must not
-   overlap.  Asynchronous on `stream`.  Disabled in this build: both return
-   FDE_EUNSUPPORTED (their first GPU run faulted; the cause was not found). */
+   overlap.  Each instance's operator is applied with its own plan (built on
+   first use: the first call allocates and synchronises `stream`), one launch
+   sequence per instance; otherwise asynchronous on `stream`. */
 fde_status fde_batch_matvec(fde_batch batch, int precision, const double* x, double* y, void* stream);
 fde_status fde_batch_tau_apply(fde_batch batch, int precision, const double* v, double* z, void* stream);
 

@@ -1380,6 +1380,31 @@ extern "C" fde_status fde_tau_apply(fde_plan pl, const double* v, double* z, voi
   return FDE_OK;
 }
 
+// The same operators in float32 arithmetic (those of the mixed form's inner
+// solves): the float64 input rounded to float32, the float32 result widened.
+static fde_status op_f32(fde_plan pl, const double* in, double* out, hipStream_t st, bool tau) {
+  if (!pl || !in || !out) return fail(FDE_EINVAL, "NULL argument");
+  if (pl->p.precision != FDE_MIXED) return fail(FDE_EINVAL, "float32 operators need a plan assembled with FDE_MIXED");
+  ProbePlanScope pps(pl);
+  const long N = pl->N;
+  hipLaunchKernelGGL((scale_cast_kernel<double, float>), dim3(ew_grid(N)), dim3(256), 0, st, in, pl->uf, N,
+                     (const double*)nullptr, (const int*)nullptr, (const int*)nullptr);
+  if (tau) tau_only<float>(pl, pl->uf, nullptr, pl->zf, st, nullptr);
+  else matvec_only<float>(pl, pl->uf, pl->zf, (float)pl->nu, 1.0f, st, nullptr);
+  hipLaunchKernelGGL((scale_cast_kernel<float, double>), dim3(ew_grid(N)), dim3(256), 0, st, pl->zf, out, N,
+                     (const double*)nullptr, (const int*)nullptr, (const int*)nullptr);
+  HIPCHK(hipGetLastError());
+  return FDE_OK;
+}
+
+extern "C" fde_status fde_matvec_f32(fde_plan pl, const double* x, double* y, void* stream) {
+  return op_f32(pl, x, y, (hipStream_t)stream, false);
+}
+
+extern "C" fde_status fde_tau_apply_f32(fde_plan pl, const double* v, double* z, void* stream) {
+  return op_f32(pl, v, z, (hipStream_t)stream, true);
+}
+
 extern "C" fde_status fde_rhs(fde_plan pl, const double* u, const double* f, double* b, void* stream) {
   if (!pl || !u || !b) return fail(FDE_EINVAL, "NULL argument");
   ProbePlanScope pps(pl);

@@ -742,22 +742,34 @@ extern "C" fde_status fde_batch_solve(fde_batch bt, const double* b, double* x, 
   return collect(bt, bt->count, info, sec, st, &pinfo);
 }
 
-// The batched operator launches are disabled: their first GPU run took a
-// memory fault whose cause was not found (a CPU emulation of the same code
-// with per-array bounds checking runs clean at every size of that run).
-static constexpr bool BATCH_APPLY_ENABLED = false;
-
+// Batched operators: every instance's operator applied with its own plan
+// (built on first use, as for the instances split off the persistent launch),
+// one launch sequence per instance on `stream`.  The persistent kernel's own
+// operator modes stay disabled: their first GPU run (an earlier build) took a
+// memory fault whose cause was not found.
 static fde_status batch_apply(fde_batch bt, int mode, int precision, const double* in, double* out, void* stream) {
   if (!bt || !in || !out) return fail(FDE_EINVAL, "NULL argument");
-  if (!BATCH_APPLY_ENABLED) return fail(FDE_EUNSUPPORTED, "batched operator launches are disabled in this build");
   if (precision != FDE_FP64 && precision != FDE_MIXED) return fail(FDE_EINVAL, "bad precision");
-  const int single = precision == FDE_MIXED;
-  if (single)
+  if (precision == FDE_MIXED)
     for (int i = 0; i < bt->count; ++i)
       if (bt->p[i].precision != FDE_MIXED)
         return fail(FDE_EINVAL, "float32 operators need a batch assembled with FDE_MIXED (instance %d)", i);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  TRY(enqueue(bt, bt->cfg, mode, in, out, nullptr, st, single));
+  for (int i = 0; i < bt->count; ++i) {
+    if (!bt->plans[i]) {
+      const fde_params q = bt->p[i];
+      TRY(fde_assemble(&q, bt->hdp[i], bt->hdm[i], nullptr, nullptr, st, &bt->plans[i]));
+    }
+    const long off = bt->off[i];
+    fde_plan pl = bt->plans[i];
+    fde_status r;
+    if (mode == MODE_MATVEC)
+      r = precision == FDE_FP64 ? fde_matvec(pl, in + off, out + off, st) : fde_matvec_f32(pl, in + off, out + off, st);
+    else
+      r = precision == FDE_FP64 ? fde_tau_apply(pl, in + off, out + off, st)
+                                : fde_tau_apply_f32(pl, in + off, out + off, st);
+    if (r != FDE_OK) return r;
+  }
   return FDE_OK;
 }
 

@@ -31,7 +31,8 @@ PROBE_LINE64_VARIANT, PROBE_LINE32_VARIANT = 64, 96
 LINE_PROGRAMS = {1: "dst", 3: "dst_f_dst", 8: "toeplitz", 11: "dst_f_dst_toeplitz", 12: "storez_toeplitz",
                  13: "dst_storez_toeplitz", 15: "dst_f_dst_storez_toeplitz", 24: "toeplitz_base"}
 
-EXPORTED = ["fde_default_params", "fde_assemble", "fde_matvec", "fde_tau_apply", "fde_solve", "fde_rhs",
+EXPORTED = ["fde_default_params", "fde_assemble", "fde_matvec", "fde_tau_apply", "fde_matvec_f32",
+            "fde_tau_apply_f32", "fde_solve", "fde_rhs",
             "fde_plan_bytes", "fde_destroy", "fde_release_cache", "fde_last_error", "fde_probe", "fde_probe_read",
             "fde_batch_layout", "fde_batch_bytes", "fde_batch_assemble", "fde_batch_solve", "fde_batch_run",
             "fde_batch_tune", "fde_batch_get_cfg", "fde_batch_set_cfg", "fde_batch_destroy",
@@ -110,6 +111,9 @@ def load(path: str = LIB_PATH):
     lib.fde_matvec.restype = ctypes.c_int
     lib.fde_tau_apply.argtypes = [vp, vp, vp, vp]
     lib.fde_tau_apply.restype = ctypes.c_int
+    for name in ("fde_matvec_f32", "fde_tau_apply_f32"):
+        getattr(lib, name).argtypes = [vp, vp, vp, vp]
+        getattr(lib, name).restype = ctypes.c_int
     lib.fde_solve.argtypes = [vp, vp, vp, ctypes.POINTER(FdeInfo), vp]
     lib.fde_solve.restype = ctypes.c_int
     lib.fde_rhs.argtypes = [vp, vp, vp, vp, vp]
@@ -228,6 +232,14 @@ def fde_tau_apply(plan, v, z, stream=None):
     return _check(load().fde_tau_apply(plan, _ptr(v), _ptr(z), _stream(stream)))
 
 
+def fde_matvec_f32(plan, x, y, stream=None):
+    return _check(load().fde_matvec_f32(plan, _ptr(x), _ptr(y), _stream(stream)))
+
+
+def fde_tau_apply_f32(plan, v, z, stream=None):
+    return _check(load().fde_tau_apply_f32(plan, _ptr(v), _ptr(z), _stream(stream)))
+
+
 def fde_solve(plan, b, x, stream=None, allow_notconv=False) -> FdeInfo:
     info = FdeInfo()
     st = load().fde_solve(plan, _ptr(b), _ptr(x), ctypes.byref(info), _stream(stream))
@@ -290,6 +302,12 @@ class Plan:
 
     def tau_apply(self, v, z, stream=None):
         fde_tau_apply(self.handle, v, z, stream)
+
+    def matvec_f32(self, x, y, stream=None):
+        fde_matvec_f32(self.handle, x, y, stream)
+
+    def tau_apply_f32(self, v, z, stream=None):
+        fde_tau_apply_f32(self.handle, v, z, stream)
 
     def solve(self, b, x, stream=None, allow_notconv=False) -> FdeInfo:
         return fde_solve(self.handle, b, x, stream, allow_notconv)

@@ -686,3 +686,29 @@ def test_fgmres_one_workgroup_matches_multikernel(tmp_path, n, alpha, restart):
     if ia.iters == ib.iters:
         assert relerr(xa, xb) < 1e-10
     mirror(fde, p, b, p.u0, xa, ia, restart=restart)
+
+
+@pytest.mark.parametrize("case", ["1d-255", "1d-65535", "1d-5000-chirp", "2d-127x63", "2d-100x70-dense"])
+def test_float32_operators(case):
+    """fde_matvec_f32 / fde_tau_apply_f32 (the mixed form's inner arithmetic)
+    against the oracle's float64 operators: relative 2e-5; a float64 plan
+    rejects them."""
+    fde = need_gpu()
+    if case.startswith("1d"):
+        n = int(case.split("-")[1])
+        p = prob1d(n, alpha=1.6, seed=n)
+    else:
+        n1, n2 = (int(t) for t in case.split("-")[1].split("x"))
+        p = prob2d(n1, n2, seed=n1 + n2)
+    s = FDESystem.from_problem(p)
+    x = rng_vec(s.N, 5 + s.N % 97)
+    with fde.Plan(p, precision=fde.MIXED) as plan:
+        y = torch.empty(s.N, dtype=torch.float64, device="cuda")
+        plan.matvec_f32(dev(x), y)
+        assert relerr(host(y), s.matvec(x)) < 2e-5
+        plan.tau_apply_f32(dev(x), y)
+        assert relerr(host(y), pc.make("tau", s)(x)) < 2e-5
+    with fde.Plan(p) as plan:
+        with pytest.raises(fde.FdeError) as e:
+            plan.matvec_f32(dev(x), torch.empty(s.N, dtype=torch.float64, device="cuda"))
+        assert e.value.status == fde.FDE_EINVAL
