@@ -335,15 +335,16 @@ def table_paper2d(fi, fde, torch, np):
 
 def table_dense(fi, fde, torch, np):
     """The line operators of 2D grids as dense products on the matrix cores
-    (MFMA) against the FFT line kernels: per n (the paper's 16 ... 128 and the
-    served 2D sizes 127, 255, 511), the time of one preconditioner application
-    plus one matrix-vector product (float64, mean of 200 pairs, events on the
-    stream) and the first implicit step of the 2D workload's coefficient
+    (MFMA) against the FFT line kernels: per n (the paper's 16 ... 128, the
+    served 2D sizes 127 ... 1023, and 1000, which only the dense form takes),
+    the time of one preconditioner application plus one matrix-vector product
+    (float64, mean of 200 pairs, events on the stream) and the first implicit
+    step of the 2D workload's coefficient
     fields solved by FGMRES(30) + P_F to 1e-8 in float64 and mixed.  Sizes
     whose n + 1 is not a power of two have only the dense form; for the others
     FDE_DENSE_LINES=1 selects it."""
     rows = []
-    for n in (16, 32, 64, 127, 128, 255, 511):
+    for n in (16, 32, 64, 127, 128, 255, 511, 1000, 1023):
         p = fi.variable_2d(n=n, steps=1)
         pow2 = ((n + 1) & n) == 0
         for form in (("lines", "dense") if pow2 else ("dense",)):
@@ -443,7 +444,7 @@ def main():
                     help="skip the per-class sampling pass; probe --probe-class in the timed region")
     ap.add_argument("--probe-class", default="line32_dst_storez_toeplitz")
     ap.add_argument("--serve-rate", type=float, default=500.0, help="Poisson arrival rate of the served leg")
-    ap.add_argument("--serve-sweep", default="2,8,50",
+    ap.add_argument("--serve-sweep", default="2,8,50,200,2000",
                     help="further arrival rates of the served leg, reported in served.sweep ('' to skip)")
     ap.add_argument("--serve-window", type=float, default=8.0,
                     help="seconds of arrivals per sweep rate (request count = rate x window, capped)")

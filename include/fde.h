@@ -23,9 +23,12 @@
  *     invalid.  fde_last_error() returns a thread-local message describing the
  *     last failure.  FDE_ENOTCONV (> 0) means the solver stopped at maxit:
  *     x then holds the last iterate and `info` is filled.
- *   - Transform sizes: every n_i + 1 must be a power of two, with
- *     2 <= n + 1 <= 2^22 in 1D and 2 <= n_i + 1 <= 4096 in 2D; other sizes
- *     return FDE_EUNSUPPORTED.
+ *   - Transform sizes.  1D: any n <= 2^21 (chirp-z sine transforms when
+ *     n + 1 is not a power of two), and n + 1 a power of two up to 2^22.
+ *     2D: n_i + 1 a power of two up to 4096 (FFT line kernels), or any
+ *     n_1, n_2 <= 1023 (the line operators as dense matrix products, whose
+ *     cost grows as n^3: meant for the paper's small grids and for sizes the
+ *     line kernels do not take).  Other sizes return FDE_EUNSUPPORTED.
  */
 #ifndef FDE_H
 #define FDE_H

@@ -42,7 +42,7 @@ extern "C" const char* fde_last_error(void) { return fde::g_err.c_str(); }
 // ---------------------------------------------------------------------------
 // Plan
 // ---------------------------------------------------------------------------
-constexpr int DENSE_NMAX = 512;       // largest n per direction of the dense 2D form
+constexpr int DENSE_NMAX = 1023;      // largest n per direction of the dense 2D form
 constexpr int CHIRP_NMAX = 1 << 21;   // largest 1D n whose n + 1 need not be a power of two
 constexpr int FOURSTEP_MIN = 4096;    // smallest four-step FFT length (both factors >= 64)
 
