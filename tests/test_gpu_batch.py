@@ -407,3 +407,34 @@ def test_batched_workload_sample_against_oracle():
     for k in np.linspace(0, len(probs) - 1, 12).astype(int):
         i = int(order[k])
         check_fp64(probs[i], xs[i], infos[i])
+
+
+def test_batched_workload_operators_against_oracle():
+    """Batched M x and P^{-1} v over the 512-instance batched workload (each
+    instance through its own plan): a sample of 16 instances spread over the
+    sizes against the oracle (float64 relative 1e-12, float32 2e-5), and for
+    every instance the float32 result within 2e-5 of the float64 one."""
+    fde = need_gpu()
+    probs = fi.batched_1d(count=512, steps=1)
+    xs = [rng_vec(p.n[0], 31 + i) for i, p in enumerate(probs)]
+    out = {}
+    with fde.Batch(probs, precision=fde.MIXED) as bt:
+        x = bt.pack(xs)
+        y = torch.empty_like(x)
+        for precision in (fde.FP64, fde.MIXED):
+            bt.matvec(x, y, precision=precision)
+            ys = bt.unpack(y)
+            bt.tau_apply(x, y, precision=precision)
+            out[precision] = (ys, bt.unpack(y))
+    for i in range(len(probs)):
+        for k in range(2):
+            assert relerr(out[fde.MIXED][k][i], out[fde.FP64][k][i]) < 2e-5, (i, probs[i].n, k)
+    order = np.argsort([p.n[0] for p in probs])
+    for k in np.linspace(0, len(probs) - 1, 16).astype(int):
+        i = int(order[k])
+        s = FDESystem.from_problem(probs[i])
+        yo, zo = s.matvec(xs[i]), pc.make("tau", s)(xs[i])
+        for precision, tol in ((fde.FP64, 1e-12), (fde.MIXED, 2e-5)):
+            ys, zs = out[precision]
+            assert relerr(ys[i], yo) < tol, (probs[i].n, precision, "matvec")
+            assert relerr(zs[i], zo) < tol, (probs[i].n, precision, "tau")
