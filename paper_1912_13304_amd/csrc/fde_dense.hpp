@@ -90,61 +90,93 @@ __global__ void __launch_bounds__(256) dense_kernel(DenseArgs<T> a) {
   if ((a.skip && *a.skip) || (a.skip2 && *a.skip2)) return;
   typedef typename Mfma<T>::v4 v4;
   const int n1 = a.n1, n2 = a.n2;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r0 = blockIdx.y * 32 + (wave >> 1) * 16;   // output rows (y index)
-  const int c0 = blockIdx.x * 32 + (wave & 1) * 16;    // output columns (x index)
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int R0 = blockIdx.y * 32, C0 = blockIdx.x * 32;   // the workgroup's 32 x 32 output tile
+  const int r0 = R0 + wr * 16;   // this wave's 16 x 16 part
+  const int c0 = C0 + wc * 16;
   const int li = lane & 15, lk = lane >> 4;
-  const int ra = r0 + li;   // row of the A operand this lane supplies
-  const int cb = c0 + li;   // column of the B operand this lane supplies
   constexpr bool ROWS = MODE == DM_ROW_DST || MODE == DM_ROW_TOEP;
   constexpr bool TOEP = MODE == DM_ROW_TOEP || MODE == DM_COL_TOEP;
   const int K = ROWS ? n1 : n2;
   const T s = (MODE == DM_ROW_DST && a.sc) ? (T)(*a.sc) : T(1);
-  v4 acc1 = {0, 0, 0, 0}, acc2 = {0, 0, 0, 0};
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    T av[4], bv[4], av2[4], bv2[4];
+  // The operands of one step of 16 along k, staged in LDS by the whole
+  // workgroup: the A panel (32 output rows x 16) and the B panel (16 x 32
+  // output columns), a second A (column Toeplitz pair) or B (row Toeplitz
+  // pair) panel.  X is loaded (rows: 16 neighbouring elements of a row,
+  // columns: 32 of a row of X), the direction's matrix generated.  Rows are
+  // padded by one element against bank conflicts.
+  constexpr int AS = 17, BS = 33;
+  __shared__ T Ap[32 * AS], Bp[16 * BS], P2[TOEP ? (ROWS ? 16 * BS : 32 * AS) : 1];
+  // thread t stages elements e = t and t + 256 of each panel:
+  // A panel (row e >> 4, k e & 15), B panel (k e >> 5, column e & 31)
+  T ra[2], rb[2], r2[2];
+  auto fetch = [&](int k0) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int k = k0 + 4 * u + lk;
+    for (int h = 0; h < 2; ++h) {
+      const int e = tid + 256 * h;
+      const int ar = R0 + (e >> 4), ak = k0 + (e & 15);   // A panel element
+      const int bk = k0 + (e >> 5), bc = C0 + (e & 31);   // B panel element
       if (ROWS) {
-        // A = X (row ra, column k); B = the x-direction matrix
         T x = T(0);
-        if (ra < n2 && k < n1) {
-          x = a.in[(long)ra * n1 + k];
+        if (ar < n2 && ak < n1) {
+          x = a.in[(long)ar * n1 + ak];
           if (MODE == DM_ROW_DST) {
             x *= s;
-            if (a.pre) x *= a.pre[(long)ra * n1 + k];
+            if (a.pre) x *= a.pre[(long)ar * n1 + ak];
           }
         }
-        av[u] = x;
+        ra[h] = x;
         if (MODE == DM_ROW_DST) {
-          bv[u] = dst_elem(a.stab, k, cb, n1);   // S1[k][c] (S symmetric)
+          rb[h] = dst_elem(a.stab, bk, bc, n1);   // S1[k][c] (S symmetric)
         } else {
-          bv[u] = toep_elem(a.g, cb, k, n1);      // (T1^T)[k][c] = T1[c][k]
-          bv2[u] = toep_elem(a.g, k, cb, n1);     // T1[k][c]
+          rb[h] = toep_elem(a.g, bc, bk, n1);     // (T1^T)[k][c] = T1[c][k]
+          r2[h] = toep_elem(a.g, bk, bc, n1);     // T1[k][c]
         }
       } else {
-        // A = the y-direction matrix (row ra, column k); B = X (row k, column cb)
-        bv[u] = (k < n2 && cb < n1) ? a.in[(long)k * n1 + cb] : T(0);
+        rb[h] = (bk < n2 && bc < n1) ? a.in[(long)bk * n1 + bc] : T(0);
         if (MODE == DM_COL_DST) {
-          av[u] = dst_elem(a.stab, ra, k, n2);
+          ra[h] = dst_elem(a.stab, ar, ak, n2);   // S2[r][k]
         } else {
-          av[u] = toep_elem(a.g, ra, k, n2);      // T2[r][k]
-          av2[u] = toep_elem(a.g, k, ra, n2);     // (T2^T)[r][k]
+          ra[h] = toep_elem(a.g, ar, ak, n2);     // T2[r][k]
+          r2[h] = toep_elem(a.g, ak, ar, n2);     // (T2^T)[r][k]
         }
       }
     }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = tid + 256 * h;
+      Ap[(e >> 4) * AS + (e & 15)] = ra[h];
+      Bp[(e >> 5) * BS + (e & 31)] = rb[h];
+      if (TOEP) {
+        if (ROWS) P2[(e >> 5) * BS + (e & 31)] = r2[h];
+        else P2[(e >> 4) * AS + (e & 15)] = r2[h];
+      }
+    }
+  };
+  v4 acc1 = {0, 0, 0, 0}, acc2 = {0, 0, 0, 0};
+  fetch(0);
+  stage();
+  __syncthreads();
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    const bool more = k0 + 16 < K;   // (the same in every thread)
+    if (more) fetch(k0 + 16);        // the next step's loads, in flight during the products
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      if (MODE == DM_ROW_TOEP) {
-        acc1 = Mfma<T>::step(av[u], bv[u], acc1);
-        acc2 = Mfma<T>::step(av[u], bv2[u], acc2);
-      } else if (MODE == DM_COL_TOEP) {
-        acc1 = Mfma<T>::step(av[u], bv[u], acc1);
-        acc2 = Mfma<T>::step(av2[u], bv[u], acc2);
-      } else {
-        acc1 = Mfma<T>::step(av[u], bv[u], acc1);
-      }
+      const int kk = 4 * u + lk;
+      const T av = Ap[(wr * 16 + li) * AS + kk];
+      const T bv = Bp[kk * BS + wc * 16 + li];
+      acc1 = Mfma<T>::step(av, bv, acc1);
+      if (MODE == DM_ROW_TOEP) acc2 = Mfma<T>::step(av, P2[kk * BS + wc * 16 + li], acc2);
+      if (MODE == DM_COL_TOEP) acc2 = Mfma<T>::step(P2[(wr * 16 + li) * AS + kk], bv, acc2);
+    }
+    if (more) {
+      __syncthreads();   // every wave has read this step's panels
+      stage();
+      __syncthreads();
     }
   }
   const int c = c0 + li;
